@@ -1,0 +1,395 @@
+"""Pins for the CPU oracle: checks against what the paper and the mathematics
+fix, independent of the oracle's own code (worked numbers printed in the
+paper, brute force on small clouds, library routines for the build arrays,
+invariants of the neighbour relations, finite differences for gradients)."""
+import math
+
+import numpy as np
+import pytest
+
+import cloudgen
+import oracle
+from tests._brute import brute_knn, brute_radius, csr_rows, sq_dist_rows
+from tests.conftest import golden
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+# --------------------------------------------------------------------------
+# clouds
+# --------------------------------------------------------------------------
+def _als(seed, n=1500):
+    return cloudgen.small_als(seed, n)
+
+
+def _walls(seed, n=1200, s=0.5):
+    """Coordinates on exact voxel walls (integer multiples of s) plus duplicates."""
+    rng = np.random.default_rng(seed)
+    g = rng.integers(0, 12, size=(n, 3)).astype(np.float64) * s
+    g[: n // 10] = g[n // 10: 2 * (n // 10)]  # exact duplicates
+    return g + np.array([1000.0, 2000.0, 10.0])
+
+
+def _blob(seed, n=800):
+    """Everything inside a single 1 m voxel."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0, 0.5, (n, 3)) + 7.0
+
+
+def _flat(seed, n=1000):
+    """Zero extent along z (n_z = 1)."""
+    rng = np.random.default_rng(seed)
+    p = rng.uniform(0, 20, (n, 3))
+    p[:, 2] = 3.25
+    return p
+
+
+CLOUDS = {"als": _als, "walls": _walls, "blob": _blob, "flat": _flat}
+
+
+def _q32(ix, xyz):
+    return (np.asarray(xyz, np.float64) - ix.origin).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# Eq. 3 -- grid size -- pinned by the voxel counts printed in Section 5.2
+# --------------------------------------------------------------------------
+def _box_cloud(ex, ey, ez, n=2000, seed=0):
+    rng = np.random.default_rng(seed)
+    p = rng.uniform(0, 1, (n, 3)) * np.array([ex, ey, ez])
+    p[0] = 0.0
+    p[1] = [ex, ey, ez]  # the two bounding-box corners
+    return p + np.array([5.0e5, 5.4e6, 0.0])
+
+
+@pytest.mark.parametrize("row", golden("voxel_counts.txt")["dales_3d"] +
+                         golden("voxel_counts.txt")["dales_2d"])
+def test_grid_size_matches_paper_voxel_counts(row):
+    ex, ey, ez, s, dims, printed, digits = row
+    ex, ey, ez, s, dims = float(ex), float(ey), float(ez), float(s), int(dims)
+    xyz = _box_cloud(ex, ey, ez)
+    ix = oracle.OracleIndex(xyz, s, dims=dims, flavor="sparse")
+    count = int(np.prod(ix.ncell))
+    mant, exp = printed.split("e")
+    scale = 10.0 ** int(exp)
+    assert round(count / scale, int(digits)) == float(mant), (count, printed)
+
+
+def test_grid_size_rules_out_ceil():
+    # a ceil-based grid would give 500 * 500 * 169 = 42.25e6 for the DALES box
+    ix = oracle.OracleIndex(_box_cloud(500.0, 500.0, 168.4), 1.0, flavor="sparse")
+    assert list(ix.ncell) == [501, 501, 169]
+    assert int(np.prod(ix.ncell)) == 42_419_169
+
+
+def test_grid_size_lille_ratio():
+    # Section 5.2: Lille Dense<2> 798.43e3 voxels, Dense<3> 34.33e6, i.e. n_z = 43,
+    # which Eq. 3 gives for any z extent in [42, 43) m at s = 1 m.
+    for ez in (42.0, 42.5, 42.999):
+        ix = oracle.OracleIndex(_box_cloud(1000.0, 797.0, ez), 1.0, flavor="sparse")
+        assert ix.ncell[2] == 43
+    assert round(798_430 * 43 / 1e6, 2) == 34.33
+
+
+# --------------------------------------------------------------------------
+# Eq. 5 / Eq. 7 -- voxel of a point and global order -- invariants
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", sorted(CLOUDS))
+@pytest.mark.parametrize("s", [0.3, 1.0, 2.5])
+@pytest.mark.parametrize("dims", [2, 3])
+def test_build_arrays(name, s, dims):
+    xyz = CLOUDS[name](11)
+    ix = oracle.OracleIndex(xyz, s, dims=dims, flavor="dense")
+    a = ix.point_arrays()
+    x32 = a["x32"]
+    # recentring: FP64 subtraction of the exact minimum, then FP32
+    np.testing.assert_array_equal(x32.T, (xyz - xyz.min(axis=0)).astype(np.float32))
+    np.testing.assert_array_equal(ix.max32, x32.max(axis=1))
+    assert ix.origin.tolist() == xyz.min(axis=0).tolist()
+    keys = a["keys"].astype(np.int64)
+    nc = ix.ncell
+    # decode g with divmod only (no geometry) and check the voxel bounds
+    i = keys // (nc[1] * nc[2]); j = (keys // nc[2]) % nc[1]; k = keys % nc[2]
+    assert (i < nc[0]).all() and (j < nc[1]).all() and (k < nc[2]).all()
+    for axis, c in ((0, i), (1, j), (2, k)):
+        if axis == 2 and dims == 2:
+            assert (c == 0).all() and nc[2] == 1
+            continue
+        v = x32[axis].astype(np.float64)
+        assert (c * s <= v * (1 + 1e-12) + 1e-12).all()
+        top = c == nc[axis] - 1
+        assert ((v < (c + 1) * s * (1 + 1e-12)) | top).all()
+        assert (nc[axis] - 1) * s <= ix.max32[axis] * (1 + 1e-12)
+    # counting sort == stable argsort; stored coordinates follow it
+    np.testing.assert_array_equal(a["perm"], np.argsort(keys, kind="stable"))
+    np.testing.assert_array_equal(a["sorted"], x32[:, a["perm"]])
+    # global order: x slowest, then y, then z (Eq. 7)
+    ijk = np.stack([i, j, k], 1)[a["perm"]]
+    lex = np.lexsort((ijk[:, 2], ijk[:, 1], ijk[:, 0]))
+    np.testing.assert_array_equal(ijk[lex], ijk)
+    # non-empty voxels and their starts == np.unique on the sorted keys
+    uk, us = ix.cells()
+    sk = keys[a["perm"]]
+    u, first = np.unique(sk, return_index=True)
+    np.testing.assert_array_equal(uk.astype(np.int64), u)
+    np.testing.assert_array_equal(us, np.append(first, len(sk)))
+    # dense start table == searchsorted over every voxel, empty ones included
+    ds = ix.dense_start()
+    np.testing.assert_array_equal(ds, np.searchsorted(sk, np.arange(int(np.prod(nc)) + 1)))
+
+
+def test_sparse_fig2_example():
+    f = golden("sparse_fig2.txt")
+    nx, ny = map(int, f["grid"][0])
+    empty = {(int(a), int(b)) for a, b in f["empty"]}
+    pts = []
+    rng = np.random.default_rng(2)
+    for i in range(nx):
+        for j in range(ny):
+            if (i, j) in empty:
+                continue
+            pts.append(np.c_[rng.uniform(i + 0.05, i + 0.95, 5), rng.uniform(j + 0.05, j + 0.95, 5),
+                             np.zeros(5)])
+    xyz = np.concatenate(pts)
+    xyz[0, :2] = 0.0
+    xyz[1, :2] = [nx - 0.01, ny - 0.01]
+    ix = oracle.OracleIndex(xyz, 1.0, dims=2, flavor="sparse")
+    assert list(ix.ncell[:2]) == [nx, ny]
+    assert ix.n_nonempty == int(f["nonempty"][0][0])
+    uk, _ = ix.cells()
+    stored = {(int(g) // ny, int(g) % ny) for g in uk}
+    assert stored.isdisjoint(empty)
+
+
+def test_kernel_box_fig3_example():
+    f = golden("kernel_box_fig3.txt")
+    nx, ny = map(int, f["grid"][0])
+    cx, cy = map(float, f["centre"][0])
+    r = float(f["radius"][0][0])
+    rng = np.random.default_rng(3)
+    xyz = np.c_[rng.uniform(0, nx - 0.01, 4000), rng.uniform(0, ny - 0.01, 4000), np.zeros(4000)]
+    xyz[0] = 0.0
+    xyz[1, :2] = [nx - 0.01, ny - 0.01]
+    ix = oracle.OracleIndex(xyz, 1.0, dims=2, flavor="dense")
+    assert list(ix.ncell[:2]) == [nx, ny]
+    off, nbr, vis = ix.radius(r, qxyz=np.array([[cx, cy, 0.0]]), visited=True)
+    assert vis[0] == int(f["box_voxels"][0][0])
+    i0, i1 = map(int, f["box_i"][0]); j0, j1 = map(int, f["box_j"][0])
+    assert (i1 - i0 + 1) * (j1 - j0 + 1) == vis[0]
+    # every neighbour lies in a voxel that meets the circle (dark grey)
+    miss = {(int(a), int(b)) for a, b in f["sphere_miss"]}
+    cells = {(int(xyz[p, 0]), int(xyz[p, 1])) for p in nbr}
+    assert cells.isdisjoint(miss) and len(cells) <= int(f["sphere_voxels"][0][0])
+    assert all(i0 <= a <= i1 and j0 <= b <= j1 for a, b in cells)
+
+
+# --------------------------------------------------------------------------
+# Alg. 1 -- radius search == brute force
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", sorted(CLOUDS))
+@pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
+@pytest.mark.parametrize("dims", [2, 3])
+@pytest.mark.parametrize("s", [0.5, 1.0, 2.5])
+def test_radius_equals_brute_force(name, flavor, dims, s):
+    xyz = CLOUDS[name](5)
+    ix = oracle.OracleIndex(xyz, s, dims=dims, flavor=flavor)
+    pts = ix.point_arrays()["x32"].T
+    rng = np.random.default_rng(1)
+    q = rng.choice(len(xyz), 120, replace=False).astype(np.int32)
+    for r in (0.0, 0.35, 1.0, 2.5):
+        off, nbr = ix.radius(r, pidx=q)
+        got = csr_rows(off, nbr)
+        want = brute_radius(pts, pts[q], r)
+        for a, b in zip(got, want):
+            np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
+def test_radius_coordinate_queries_outside_bbox(flavor):
+    xyz = _als(7)
+    ix = oracle.OracleIndex(xyz, 1.0, flavor=flavor)
+    pts = ix.point_arrays()["x32"].T
+    rng = np.random.default_rng(2)
+    lo, hi = xyz.min(0), xyz.max(0)
+    qa = rng.uniform(lo - 3.0, hi + 3.0, (200, 3))
+    for r in (0.5, 2.0, 4.0):
+        off, nbr = ix.radius(r, qxyz=qa)
+        want = brute_radius(pts, _q32(ix, qa), r)
+        for a, b in zip(csr_rows(off, nbr), want):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_radius_degenerate_cases():
+    xyz = _walls(3)
+    ix = oracle.OracleIndex(xyz, 0.5)
+    pts = ix.point_arrays()["x32"].T
+    n = len(xyz)
+    # r larger than the bounding-box diagonal: every point
+    off, nbr = ix.radius(100.0, pidx=np.arange(0, n, 37, dtype=np.int32))
+    assert (np.diff(off) == n).all()
+    # r = 0: the point itself plus its exact duplicates
+    q = np.arange(n, dtype=np.int32)
+    off, nbr = ix.radius(0.0, pidx=q)
+    for t, row in enumerate(csr_rows(off, nbr)):
+        same = np.nonzero((pts == pts[t]).all(1))[0]
+        np.testing.assert_array_equal(row, same)
+    # a single-point cloud
+    one = oracle.OracleIndex(np.array([[1.0, 2.0, 3.0]]), 1.0)
+    assert list(one.ncell) == [1, 1, 1]
+    off, nbr = one.radius(0.0, pidx=np.array([0], np.int32))
+    assert off.tolist() == [0, 1] and nbr.tolist() == [0]
+
+
+def test_radius_symmetry_and_monotonicity():
+    xyz = _als(9, 3000)
+    ix = oracle.OracleIndex(xyz, 1.0)
+    n = len(xyz)
+    prev = None
+    for r in (0.3, 0.7, 1.5, 3.0):
+        off, nbr = ix.radius(r)
+        rows = np.repeat(np.arange(n), np.diff(off))
+        pairs = set(zip(rows.tolist(), nbr.tolist()))
+        assert all((b, a) in pairs for a, b in pairs)  # j in N(i) <=> i in N(j)
+        assert all((a, a) in pairs for a in range(n))  # self included
+        if prev is not None:
+            assert prev <= pairs  # monotone in r
+        prev = pairs
+
+
+def test_distance_error_bound():
+    # the FP32 distance stays within a few ulps of the exact FP64 value
+    rng = np.random.default_rng(0)
+    a = rng.uniform(0, 1000, (5000, 3)).astype(np.float32)
+    b = (a + rng.normal(0, 3, a.shape)).astype(np.float32)
+    D = np.array([sq_dist_rows(a[t:t + 1], b[t:t + 1])[0, 0] for t in range(len(a))])
+    exact = ((a.astype(np.float64) - b.astype(np.float64)) ** 2).sum(1)
+    assert (np.abs(D - exact) <= 4 * 2.0 ** -24 * exact + 1e-30).all()
+
+
+# --------------------------------------------------------------------------
+# Alg. 2 -- k-NN == brute force (stable sort by (D, index))
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", sorted(CLOUDS))
+@pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
+@pytest.mark.parametrize("dims", [2, 3])
+@pytest.mark.parametrize("s", [0.5, 2.5])
+def test_knn_equals_brute_force(name, flavor, dims, s):
+    xyz = CLOUDS[name](4)
+    ix = oracle.OracleIndex(xyz, s, dims=dims, flavor=flavor)
+    pts = ix.point_arrays()["x32"].T
+    rng = np.random.default_rng(3)
+    q = rng.choice(len(xyz), 100, replace=False).astype(np.int32)
+    for k in (1, 8, 33):
+        idx, d2 = ix.knn(k, pidx=q)
+        bi, bd = brute_knn(pts, pts[q], k)
+        np.testing.assert_array_equal(idx, bi)
+        np.testing.assert_array_equal(d2, bd)
+
+
+def test_knn_coordinate_queries_and_rmax():
+    xyz = _als(8)
+    ix = oracle.OracleIndex(xyz, 1.0, flavor="sparse")
+    pts = ix.point_arrays()["x32"].T
+    rng = np.random.default_rng(5)
+    qa = rng.uniform(xyz.min(0) - 5.0, xyz.max(0) + 5.0, (150, 3))
+    for rmax in (math.inf, 0.7, 2.0):
+        idx, d2 = ix.knn(12, r_max=rmax, qxyz=qa)
+        bi, bd = brute_knn(pts, _q32(ix, qa), 12, r_max=rmax)
+        np.testing.assert_array_equal(idx, bi)
+        np.testing.assert_array_equal(d2, bd)
+
+
+def test_knn_invariants():
+    xyz = _walls(6, 600)
+    n = len(xyz)
+    ix = oracle.OracleIndex(xyz, 0.5, flavor="mixed")
+    q = np.arange(0, n, 7, dtype=np.int32)
+    i8, d8 = ix.knn(8, pidx=q)
+    i20, d20 = ix.knn(20, pidx=q)
+    np.testing.assert_array_equal(i20[:, :8], i8)  # k-prefix
+    np.testing.assert_array_equal(d20[:, :8], d8)
+    # k > N: all N points, then padding
+    ib, db = ix.knn(n + 5, pidx=q[:3])
+    assert (ib[:, :n] >= 0).all() and (ib[:, n:] == -1).all() and np.isinf(db[:, n:]).all()
+    assert all(sorted(row[:n].tolist()) == list(range(n)) for row in ib)
+    # d2[k-1] <= R  <=>  |N_r| >= k
+    r = 0.8
+    off, _ = ix.radius(r, pidx=q)
+    R = np.float32(r) * np.float32(r)
+    np.testing.assert_array_equal(d20[:, 19] <= R, np.diff(off) >= 20)
+    # first neighbour is the point itself unless a duplicate has a lower index
+    pts = ix.point_arrays()["x32"].T
+    for t, p in enumerate(q):
+        dup = np.nonzero((pts == pts[p]).all(1))[0]
+        assert i8[t, 0] == dup.min() and d8[t, 0] == 0.0
+
+
+# --------------------------------------------------------------------------
+# mixed flavor: a slice is dense once 80 % of its voxels hold points
+# --------------------------------------------------------------------------
+def test_mixed_slice_rule():
+    nx, ny = 10, 10
+    need = math.ceil(0.8 * nx * ny)  # 80 voxels
+    for filled, dense in ((need, True), (need - 1, False)):
+        cells = [(i, j) for i in range(nx) for j in range(ny)][:filled]
+        pts = [[i + 0.5, j + 0.5, 0.5] for i, j in cells]
+        pts += [[0.0, 0.0, 0.0], [nx - 0.01, ny - 0.01, 1.99]]  # corners; slice 1 sparse
+        ix = oracle.OracleIndex(np.array(pts), 1.0, flavor="mixed")
+        ne, de = ix.slices()
+        assert list(ix.ncell) == [nx, ny, 2]
+        assert ne[0] == filled + (0 if (0, 0) in cells else 1)
+        assert bool(de[0]) == dense and not de[1]
+
+
+# --------------------------------------------------------------------------
+# aggregation (project addition): FP64 forward and analytic gradient
+# --------------------------------------------------------------------------
+def _agg_case(seed=0, n=60, q=15, k=6, c=4):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0, 1.0, (n, 3))
+    f = rng.standard_normal((n, c))
+    qidx = rng.choice(n, q, replace=False).astype(np.int32)
+    nbr = rng.integers(-1, n, (q, k)).astype(np.int32)
+    nbr[:, 0] = qidx  # self in the list
+    return x, f, qidx, nbr
+
+
+def test_agg_special_cases():
+    x, f, qidx, nbr = _agg_case()
+    # sigma -> infinity: every weight is 1, out = plain sum of the features
+    out = oracle.agg_forward(x, qidx, nbr, f, 1e9)
+    want = np.stack([f[row[row >= 0]].sum(0) for row in nbr])
+    np.testing.assert_allclose(out, want, rtol=1e-12, atol=1e-12)
+    # a neighbour list holding only the centre itself returns its feature
+    only = np.full_like(nbr, -1); only[:, 0] = qidx
+    np.testing.assert_array_equal(oracle.agg_forward(x, qidx, only, f, 0.3), f[qidx])
+    # two points at distance d: out = f[q] + exp(-d^2 / (2 sigma^2)) f[j]
+    x2 = np.array([[0.0, 0, 0], [0.3, 0.4, 0]]); f2 = np.array([[1.0, 2.0], [3.0, -1.0]])
+    o = oracle.agg_forward(x2, np.array([0], np.int32), np.array([[0, 1]], np.int32), f2, 0.5)
+    w = math.exp(-0.25 / 0.5)
+    np.testing.assert_allclose(o[0], [1 + 3 * w, 2 - w], rtol=1e-14)
+
+
+def test_agg_gradient_finite_differences():
+    x, f, qidx, nbr = _agg_case(1)
+    sigma = 0.35
+    rng = np.random.default_rng(9)
+    g = rng.standard_normal((len(qidx), f.shape[1]))
+    gx, gf = oracle.agg_backward(x, qidx, nbr, f, sigma, g)
+
+    def L(xx, ff):
+        return float((oracle.agg_forward(xx, qidx, nbr, ff, sigma) * g).sum())
+
+    h = 1e-6
+    num_x = np.zeros_like(x)
+    for p in range(x.shape[0]):
+        for a in range(3):
+            e = np.zeros_like(x); e[p, a] = h
+            num_x[p, a] = (L(x + e, f) - L(x - e, f)) / (2 * h)
+    num_f = np.zeros_like(f)
+    for p in range(f.shape[0]):
+        for c in range(f.shape[1]):
+            e = np.zeros_like(f); e[p, c] = h
+            num_f[p, c] = (L(x, f + e) - L(x, f - e)) / (2 * h)
+    np.testing.assert_allclose(gx, num_x, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(gf, num_f, rtol=1e-6, atol=1e-7)
