@@ -1,0 +1,238 @@
+#!/usr/bin/env python
+"""Benchmark of the grid-index hot path on one MI355X.
+
+One step = one pass of the whole path over the large ALS tile (10 M points
+over 1 km x 1 km, every point a query): build the index (bounding box, voxel
+keys, counting-sort reordering, dense voxel map, 1 m cells), plan the query
+order, then fixed-radius search (count + prefix sum + fill) at r = 0.5, 1, 2
+and 3 m and k-NN at k = 8, 16 and 32.  Inputs are resident in HBM before the
+timed region; each call's results are produced in full (CSR neighbour lists,
+[Q,k] indices and squared distances).
+
+Prints one JSON line.  ``value`` is queries answered per second over the
+whole step (7 query batches of N queries, index build included).
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "radius/k-NN queries per sec at 1 GPU; achieved HBM GB/s vs peak; build Mpts/s"
+PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2502_11602_amd/csrc/search.hip", "paper_2502_11602_amd/csrc/common.h"]
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel, radius):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 PMC
+    summary, or None when there is none or the kernel sources changed since
+    the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "radius_fill_als10m_pmc.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    ent = d.get("per_launch_bytes", {}).get(f"{kernel}@r={radius}")
+    return ent
+
+
+def cpu_baseline(xyz, radii, ks, cell, sample, nthreads):
+    """The oracle as it stands, on the host cores: full build plus a seeded
+    sample of queries per radius / k, scaled to the whole step."""
+    import numpy as np
+
+    import oracle
+
+    n = xyz.shape[0]
+    q = np.sort(np.random.default_rng(99).choice(n, sample, replace=False)).astype(np.int32)
+    t0 = time.perf_counter()
+    ox = oracle.OracleIndex(xyz, cell)
+    t_build = time.perf_counter() - t0
+    per_q = 0.0
+    for r in radii:
+        t0 = time.perf_counter()
+        ox.radius(r, pidx=q, nthreads=nthreads)
+        per_q += (time.perf_counter() - t0) / sample
+    for k in ks:
+        t0 = time.perf_counter()
+        ox.knn(k, pidx=q, nthreads=nthreads)
+        per_q += (time.perf_counter() - t0) / sample
+    t_step = t_build + per_q * n
+    nops = len(radii) + len(ks)
+    return {
+        "value": nops * n / t_step,
+        "unit": "queries/s",
+        "cores": nthreads,
+        "kind": "oracle",
+        "sample": (f"full oracle build of the {n}-point cloud ({t_build:.1f} s, one thread) plus "
+                   f"{sample} seeded point queries per radius and per k on {nthreads} threads, "
+                   f"scaled to {n} queries per batch"),
+        "build_s": t_build,
+        "query_us_per_thread": per_q * 1e6 * nthreads / nops,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--radii", default="0.5,1,2,3")
+    ap.add_argument("--ks", default="8,16,32")
+    ap.add_argument("--flavor", default="dense")
+    ap.add_argument("--cell", type=float, default=1.0)
+    ap.add_argument("--points", type=int, default=10_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=20_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(queries shard independently; see the design notes). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import cloudgen
+    from paper_2502_11602_amd import GridIndex
+
+    radii = [float(v) for v in args.radii.split(",") if v]
+    ks = [int(v) for v in args.ks.split(",") if v]
+    print(f"[bench] generating ALS tile: {args.points} points", file=sys.stderr, flush=True)
+    cfg = cloudgen.config1(n=args.points)
+    xyz = cfg["xyz"]
+    n = xyz.shape[0]
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(xyz).to(dev)
+    torch.cuda.synchronize()
+
+    E = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def step(rec):
+        ev = {"start": E()}
+        ev["start"].record()
+        ix = GridIndex(x, cell=args.cell, flavor=args.flavor)
+        ev["build"] = E(); ev["build"].record()
+        # the "every point" query order is planned by the first search on the
+        # index and cached on it, so the first count below includes it
+        totals = {}
+        for r in radii:
+            off, tot = ix.radius_count(r)
+            ev[f"count{r}"] = E(); ev[f"count{r}"].record()
+            nbr = ix.radius_fill(r, off, tot)
+            ev[f"fill{r}"] = E(); ev[f"fill{r}"].record()
+            totals[r] = tot
+            del nbr, off
+        for k in ks:
+            idx, d2 = ix.knn(k)
+            ev[f"knn{k}"] = E(); ev[f"knn{k}"].record()
+            del idx, d2
+        ix.close()
+        if rec is not None:
+            rec.append((ev, totals))
+
+    for w in range(args.warmup):
+        step(None)
+        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(recs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    print(f"[bench] {args.steps} timed steps in {wall:.3f} s", file=sys.stderr, flush=True)
+
+    def avg(a, b):
+        return sum(ev[a].elapsed_time(ev[b]) for ev, _ in recs) / len(recs)
+
+    names = ["start", "build"]
+    for r in radii:
+        names += [f"count{r}", f"fill{r}"]
+    names += [f"knn{k}" for k in ks]
+    phase = {names[i]: avg(names[i - 1], names[i]) for i in range(1, len(names))}
+    totals = recs[-1][1]
+    ms_step = wall * 1e3 / args.steps
+    nops = len(radii) + len(ks)
+    value = nops * n / (ms_step / 1e3)
+
+    radius = {}
+    for r in radii:
+        ms = phase[f"count{r}"] + phase[f"fill{r}"]
+        radius[str(r)] = {"count_ms": phase[f"count{r}"], "fill_ms": phase[f"fill{r}"],
+                          "queries_per_s": n / (ms / 1e3), "neighbours": totals[r],
+                          "mean_neighbours": totals[r] / n}
+    knn = {str(k): {"ms": phase[f"knn{k}"], "queries_per_s": n / (phase[f"knn{k}"] / 1e3)}
+           for k in ks}
+
+    # roofline of the dominant kernel: the radius fill at the largest radius
+    # (it writes the CSR lists).  Algorithmic bytes per launch: query records
+    # 16 B x Q + row offsets 8 B x Q + every stored point at least once 16 B x N
+    # + neighbour indices 4 B x T.
+    rdom = max(radii)
+    T = totals[rdom]
+    alg_bytes = 16 * n + 8 * n + 16 * n + 4 * T
+    fill_s = phase[f"fill{rdom}"] / 1e3
+    achieved = alg_bytes / fill_s / 1e9
+    roof = {"kernel": "k_radius<fill>", "radius_m": rdom, "bound": "hbm", "achieved": achieved,
+            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+            "traffic": counter_traffic("k_radius<fill>", rdom),
+            "algorithmic_bytes": alg_bytes, "launch_ms": phase[f"fill{rdom}"]}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"ALS tile, {n} points over 1 km x 1 km (terrain, buildings, "
+                         "multi-return vegetation), every point a query; build "
+                         f"({args.flavor}, {args.cell} m voxels) + radius search r in "
+                         f"{radii} m + k-NN k in {ks}"),
+            "n_points": n, "queries_per_batch": n, "radii_m": radii, "ks": ks,
+            "flavor": args.flavor, "cell_m": args.cell,
+        },
+        "build_ms": phase["build"],
+        "build_mpts_s": n / (phase["build"] / 1e3) / 1e6,
+        "radius": radius,
+        "knn": knn,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        nth = len(os.sched_getaffinity(0))
+        print(f"[bench] cpu baseline: oracle on {nth} threads", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(xyz, radii, ks, args.cell, args.cpu_sample, nth)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,194 @@
+/* chs.h -- C ABI of the MI355X grid point index (Cheesemap, Laso & Yermo,
+ * arXiv 2502.11602).
+ *
+ * The index is the paper's uniform voxel grid (Section 3.2) stored in one of
+ * its three flavors (Section 3.3: dense, sparse, mixed), built on the GPU by
+ * keying every point with its voxel's global index (Eq. 5-7), counting the
+ * points per voxel, prefix-summing the counts and scattering the points into
+ * voxel order (the reordering of Section 3.5).  It answers batches of
+ * fixed-radius sphere queries (the kernel-based search of Section 3.4.1,
+ * Alg. 1) and k-nearest-neighbour queries (Section 3.4.2, Alg. 2).
+ *
+ * Conventions shared by every call:
+ *  - Array pointers are DEVICE pointers unless marked (host).  Every call is
+ *    enqueued on `stream`; only the calls documented as synchronising wait
+ *    for it.
+ *  - Inputs are borrowed for the duration of the call.  Outputs of fixed size
+ *    are allocated by the caller.  Memory the library keeps (the index) or
+ *    needs temporarily comes from the `chs_allocator` given to chs_build; a
+ *    NULL allocator means stream-ordered hipMallocAsync / hipFreeAsync.
+ *  - Calls never abort.  They return a chs_status; on failure the message of
+ *    chs_last_error() says why, the caller's outputs are left untouched
+ *    unless stated otherwise, and nothing leaks.  Arguments are validated on
+ *    the host before anything is enqueued.
+ *  - Geometry: coordinates are FP64 [n,3] row-major (x, y, z), absolute.  The
+ *    index recentres them on the cloud's minimum corner p- (Eq. 1) in FP64
+ *    and stores FP32.  The squared distance of a point p to a centre c is the
+ *    unfused FP32 value D = (dx*dx + dy*dy) + dz*dz with dx = fl32(c_x - p_x),
+ *    and a point is inside a sphere of radius r when D <= fl32(r*r) (closed
+ *    sphere).  Results are bit-exact against that definition.
+ */
+#ifndef CHS_H
+#define CHS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum chs_status {
+  CHS_OK = 0,
+  CHS_E_INVALID = 1,     /* bad argument (NULL, size, non-finite, range)      */
+  CHS_E_NOMEM = 2,       /* the allocator returned NULL                        */
+  CHS_E_CAPACITY = 3,    /* a table would exceed its limit (dense voxel count) */
+  CHS_E_DEVICE = 4,      /* a HIP runtime error                                */
+  CHS_E_UNSUPPORTED = 5  /* valid but not implemented for this configuration   */
+} chs_status;
+
+/* Voxel storage, Section 3.3: DENSE keeps every voxel of the grid (3.3.1),
+ * SPARSE keeps only non-empty voxels in a hash map keyed by the global index
+ * (3.3.2), MIXED splits the grid into z-slices, each dense once at least
+ * mixed_dense_pct percent of its voxels hold points and sparse otherwise
+ * (3.3.3). */
+typedef enum chs_flavor { CHS_DENSE = 0, CHS_SPARSE = 1, CHS_MIXED = 2 } chs_flavor;
+
+typedef struct chs_allocator {
+  void* (*alloc)(size_t bytes, void* ctx); /* device memory, >= 256-byte aligned */
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} chs_allocator;
+
+typedef struct chs_build_params {
+  int32_t flavor;          /* chs_flavor                                        */
+  int32_t dims;            /* 3: voxels on x,y,z; 2: columns on x,y (n_z = 1)   */
+  double cell[3];          /* voxel edge per axis in metres, > 0 (Section 3.2,
+                              footnote: edges may differ per axis); cell[2] is
+                              ignored when dims == 2                            */
+  int32_t mixed_dense_pct; /* MIXED: slice turns dense at this percentage of
+                              non-empty voxels (the paper's default is 80)      */
+  int32_t reserved;        /* must be 0                                         */
+  int64_t max_dense_cells; /* DENSE: refuse grids with more voxels (0 = 2^31-2) */
+} chs_build_params;
+
+typedef struct chs_index_s* chs_index;
+
+/* A batch of query centres.  Exactly one of:
+ *   xyz       [nq,3] FP64 absolute coordinates (recentred by the library),
+ *   point_idx [nq]   int32 indices into the indexed cloud (the centre is that
+ *                    point's stored FP32 position; the paper's benchmark
+ *                    queries are cloud points, Section 4.4),
+ *   neither          every indexed point, in index order (nq must equal n).
+ * nq == 0 is an empty batch whatever the pointers.  A point index outside
+ * [0, n) or a non-finite coordinate makes an empty query (no neighbours,
+ * k-NN row of (-1, +inf)).  Row q of every result belongs to the caller's
+ * q-th query. */
+typedef struct chs_queries {
+  const double* xyz;
+  const int32_t* point_idx;
+  int64_t nq;
+} chs_queries;
+
+/* Build the index over n points xyz [n,3] (FP64, device).  Computes the
+ * bounding box p-, p+ (Eq. 1-2), the grid size n_a = floor((p+_a - p-_a)/s_a)
+ * + 1 (Eq. 3), each point's voxel (Eq. 5, 0-based, clamped to n_a - 1) and
+ * global index g = (i*n_y + j)*n_z + k (Eq. 6-7), the per-voxel counts, their
+ * exclusive prefix sum and the stable scatter of the points into voxel order
+ * (ascending g, then ascending original index), and the flavor's voxel map.
+ * Synchronises `stream` to size the grid from the bounding box and the
+ * voxel tables from the number of non-empty voxels (and, for MIXED, the
+ * per-slice counts).  n in [1, 2^31 - 1].  Non-finite coordinates give CHS_E_INVALID; a dense
+ * grid above max_dense_cells gives CHS_E_CAPACITY.  On success *out (host)
+ * owns its device memory until chs_free. */
+chs_status chs_build(const double* xyz, int64_t n, const chs_build_params* params,
+                     const chs_allocator* alloc, hipStream_t stream, chs_index* out);
+
+typedef struct chs_index_info_t {
+  double origin[3];     /* p-, FP64                                      */
+  float max32[3];       /* p+ - p- after recentring, FP32                */
+  double cell[3];
+  int64_t ncell[3];     /* n_x, n_y, n_z                                  */
+  int64_t n_points;
+  int64_t n_nonempty;   /* voxels holding at least one point             */
+  int64_t n_dense_slices; /* MIXED: slices stored densely                 */
+  int64_t device_bytes; /* memory held by the index                      */
+  int32_t flavor, dims;
+} chs_index_info_t;
+
+/* Host-side description of a built index.  No device work. */
+chs_status chs_index_info(chs_index index, chs_index_info_t* out /* host */);
+
+/* Device arrays of a built index, borrowed (valid until chs_free, never to
+ * be written).  perm[pos] = original index of the pos-th stored point;
+ * inv_perm = its inverse; sorted_xyz = SoA [3][n] FP32 recentred coordinates
+ * in stored order; points = [n] x,y,z,FP32 + original index (int32 bits) in
+ * stored order; cell_keys [M] = ascending non-empty global voxel indices
+ * (uint64); cell_start [M+1] = first stored position of each, then n;
+ * dense_start [n_x*n_y*n_z + 1] (DENSE only, else NULL) = first stored
+ * position of every voxel; slice_dense [n_z] (MIXED only, else NULL) = 1
+ * when slice k is stored densely. */
+typedef struct chs_index_arrays_t {
+  const int32_t* perm;
+  const int32_t* inv_perm;
+  const float* sorted_xyz;
+  const float* points;
+  const uint64_t* cell_keys;
+  const int32_t* cell_start;
+  const int32_t* dense_start;
+  const uint8_t* slice_dense;
+} chs_index_arrays_t;
+
+chs_status chs_index_arrays(chs_index index, chs_index_arrays_t* out /* host */);
+
+/* Fixed-radius search, count pass (Alg. 1 with a spherical kernel B(c, r),
+ * Section 3.4.1): offsets [nq+1] (int64, device) receives the exclusive
+ * prefix sum of the per-query neighbour counts |{p : D(c, p) <= fl32(r*r)}|,
+ * and *total (host) its last entry.  Synchronises `stream` to read total.
+ * r must be finite and >= 0. */
+chs_status chs_radius_count(chs_index index, const chs_queries* queries, float r,
+                            int64_t* offsets, int64_t* total, hipStream_t stream);
+
+/* Fill pass: writes the original indices of each query's neighbours into
+ * nbr[offsets[q] .. offsets[q+1]) (int32, device, `total` entries, as given
+ * by chs_radius_count for the same queries and r).  The order inside a row
+ * is deterministic but unspecified (the neighbour relation is a set). */
+chs_status chs_radius_fill(chs_index index, const chs_queries* queries, float r,
+                           const int64_t* offsets, int32_t* nbr, int64_t total,
+                           hipStream_t stream);
+
+/* count + allocation of the neighbour array through `alloc` (NULL = the
+ * index's allocator) + fill.  *nbr (host) receives the device pointer, which
+ * the caller releases with the same allocator (or hipFree for NULL); it is
+ * NULL when total is 0.  Synchronises `stream` once. */
+chs_status chs_radius_search(chs_index index, const chs_queries* queries, float r,
+                             const chs_allocator* alloc, int64_t* offsets, int32_t** nbr,
+                             int64_t* total, hipStream_t stream);
+
+/* k-nearest-neighbour search (Section 3.4.2): for every query, the min(k, n)
+ * points first in the order (D, original index), written to idx [nq,k]
+ * (int32) and their squared distances D to d2 [nq,k] (FP32), ascending;
+ * with a finite r_max only entries with D <= fl32(r_max*r_max) are kept.
+ * Missing entries are (-1, +inf).  1 <= k <= 64; r_max >= 0 or +inf.
+ * Does not synchronise. */
+chs_status chs_knn(chs_index index, const chs_queries* queries, int32_t k, float r_max,
+                   int32_t* idx, float* d2, hipStream_t stream);
+
+/* Release the index and its device memory (stream-ordered on the stream it
+ * was built with).  NULL is ignored. */
+void chs_free(chs_index index);
+
+/* Message of the last failure on the calling thread ("" if none).  Valid
+ * until the next call on the same thread. */
+const char* chs_last_error(void);
+
+/* Library version string, e.g. "chs 0.1.0 gfx950". */
+const char* chs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHS_H */

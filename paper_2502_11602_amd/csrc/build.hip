@@ -1,0 +1,571 @@
+// Index construction on the GPU (Section 3.1-3.3 and the reordering remark
+// of Section 3.5):
+//   bounding box (Eq. 1-2) -> grid size (Eq. 3) -> per-point voxel and global
+//   index (Eq. 5-7) -> stable sort by global index (LSD radix: a chain of
+//   stable counting sorts on 8-bit digits, so points inside a voxel keep
+//   ascending original index) -> non-empty voxels and their starts (per-voxel
+//   counts and exclusive prefix sum) -> the flavor's voxel map.
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+#pragma clang fp contract(off)
+
+namespace chs {
+
+constexpr int kThreads = 256;
+
+static unsigned grid_for(int64_t n, int per_block = kThreads) {
+  int64_t b = (n + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+// ---------------------------------------------------------------- bbox
+constexpr int kBoxBlocks = 1024;
+
+__global__ __launch_bounds__(kThreads) void k_bbox(const double* __restrict__ xyz, int64_t n,
+                                                   double* __restrict__ part) {
+  double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  double bad = 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < n;
+       p += (int64_t)gridDim.x * kThreads) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double v = xyz[p * 3 + a];
+      if (!isfinite(v)) bad = 1.0;
+      mn[a] = v < mn[a] ? v : mn[a];
+      mx[a] = v > mx[a] ? v : mx[a];
+    }
+  }
+  __shared__ double s[kThreads / kWave][7];
+  const int w = threadIdx.x / kWave;
+  double r[7];
+  for (int a = 0; a < 3; ++a) {
+    r[a] = wave_min(mn[a]);
+    r[3 + a] = wave_max(mx[a]);
+  }
+  r[6] = wave_max(bad);
+  if (lane_id() == 0)
+    for (int a = 0; a < 7; ++a) s[w][a] = r[a];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < kThreads / kWave; ++q) {
+      for (int a = 0; a < 3; ++a) {
+        r[a] = s[q][a] < r[a] ? s[q][a] : r[a];
+        r[3 + a] = s[q][3 + a] > r[3 + a] ? s[q][3 + a] : r[3 + a];
+      }
+      r[6] = s[q][6] > r[6] ? s[q][6] : r[6];
+    }
+    for (int a = 0; a < 7; ++a) part[blockIdx.x * 7 + a] = r[a];
+  }
+}
+
+__global__ void k_bbox_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double r[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0};
+  for (int b = 0; b < nb; ++b) {
+    for (int a = 0; a < 3; ++a) {
+      r[a] = part[b * 7 + a] < r[a] ? part[b * 7 + a] : r[a];
+      r[3 + a] = part[b * 7 + 3 + a] > r[3 + a] ? part[b * 7 + 3 + a] : r[3 + a];
+    }
+    r[6] = part[b * 7 + 6] > r[6] ? part[b * 7 + 6] : r[6];
+  }
+  for (int a = 0; a < 7; ++a) out[a] = r[a];
+}
+
+// ---------------------------------------------------------------- keys
+struct KeyArgs {
+  double origin[3];
+  double s[3];
+  int64_t n[3];
+  int32_t dims;
+};
+
+template <class K>
+__global__ __launch_bounds__(kThreads) void k_keys(const double* __restrict__ xyz, int64_t n,
+                                                   KeyArgs ka, K* __restrict__ keys,
+                                                   uint32_t* __restrict__ vals,
+                                                   float4* __restrict__ xyz4) {
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (p >= n) return;
+  float c[3];
+  int64_t v[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    c[a] = (float)(xyz[p * 3 + a] - ka.origin[a]);  // FP64 recentring, then FP32
+    if (a < ka.dims) v[a] = voxel_clamped((double)c[a], ka.s[a], ka.n[a]);
+  }
+  const uint64_t g = ((uint64_t)v[0] * (uint64_t)ka.n[1] + (uint64_t)v[1]) * (uint64_t)ka.n[2] +
+                     (uint64_t)v[2];
+  keys[p] = (K)g;
+  vals[p] = (uint32_t)p;
+  xyz4[p] = make_float4(c[0], c[1], c[2], __int_as_float((int)p));
+}
+
+__global__ __launch_bounds__(kThreads) void k_gather_points(
+    const uint32_t* __restrict__ perm_u, const float4* __restrict__ xyz4, int64_t n,
+    float4* __restrict__ pts, float* __restrict__ sxyz, int32_t* __restrict__ perm,
+    int32_t* __restrict__ inv_perm) {
+  const int64_t pos = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (pos >= n) return;
+  const uint32_t p = perm_u[pos];
+  const float4 c = xyz4[p];
+  pts[pos] = c;
+  sxyz[pos] = c.x;
+  sxyz[n + pos] = c.y;
+  sxyz[2 * n + pos] = c.z;
+  perm[pos] = (int32_t)p;
+  inv_perm[p] = (int32_t)pos;
+}
+
+// ---------------------------------------------------------------- non-empty voxels
+template <class K>
+__global__ __launch_bounds__(kThreads) void k_run_heads(const K* __restrict__ skeys, int64_t n,
+                                                        int32_t* __restrict__ flag) {
+  const int64_t pos = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (pos >= n) return;
+  flag[pos] = (pos == 0 || skeys[pos] != skeys[pos - 1]) ? 1 : 0;
+}
+
+template <class K>
+__global__ __launch_bounds__(kThreads) void k_compact_voxels(const K* __restrict__ skeys,
+                                                             const int32_t* __restrict__ flag,
+                                                             const int32_t* __restrict__ uidx,
+                                                             int64_t n, uint64_t* __restrict__ ukeys,
+                                                             int32_t* __restrict__ ustart) {
+  const int64_t pos = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (pos > n) return;
+  if (pos == n) {
+    ustart[uidx[n]] = (int32_t)n;
+    return;
+  }
+  if (flag[pos]) {
+    const int32_t u = uidx[pos];
+    ukeys[u] = (uint64_t)skeys[pos];
+    ustart[u] = (int32_t)pos;
+  }
+}
+
+// ---------------------------------------------------------------- dense map
+__global__ __launch_bounds__(kThreads) void k_fill_i32(int32_t* __restrict__ a, int64_t n,
+                                                       int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    a[i] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill_u64(uint64_t* __restrict__ a, int64_t n,
+                                                       uint64_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    a[i] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_voxel_counts(const uint64_t* __restrict__ ukeys,
+                                                           const int32_t* __restrict__ ustart,
+                                                           int64_t M, int32_t* __restrict__ cnt) {
+  const int64_t u = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (u >= M) return;
+  cnt[ukeys[u]] = ustart[u + 1] - ustart[u];
+}
+
+// ---------------------------------------------------------------- sparse map
+__device__ void hash_insert(uint64_t* hk, int32_t* hv, uint64_t mask, uint64_t g, int32_t u) {
+  uint64_t h = mix64(g) & mask;
+  while (true) {
+    const unsigned long long prev =
+        atomicCAS((unsigned long long*)&hk[h], (unsigned long long)kEmptyKey,
+                  (unsigned long long)g);
+    if (prev == kEmptyKey) {
+      hv[h] = u;
+      return;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_hash_build(const uint64_t* __restrict__ ukeys,
+                                                         int64_t M, uint64_t* hk, int32_t* hv,
+                                                         uint64_t mask) {
+  const int64_t u = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (u >= M) return;
+  hash_insert(hk, hv, mask, ukeys[u], (int32_t)u);
+}
+
+// ---------------------------------------------------------------- mixed map
+__global__ __launch_bounds__(kThreads) void k_slice_counts(const uint64_t* __restrict__ ukeys,
+                                                           int64_t M, int64_t nz,
+                                                           int32_t* __restrict__ cnt) {
+  extern __shared__ int32_t sh[];
+  const bool priv = nz <= 4096;
+  if (priv) {
+    for (int64_t i = threadIdx.x; i < nz; i += kThreads) sh[i] = 0;
+    __syncthreads();
+  }
+  for (int64_t u = (int64_t)blockIdx.x * kThreads + threadIdx.x; u < M;
+       u += (int64_t)gridDim.x * kThreads) {
+    const int64_t k = (int64_t)(ukeys[u] % (uint64_t)nz);
+    if (priv)
+      atomicAdd(&sh[k], 1);
+    else
+      atomicAdd(&cnt[k], 1);
+  }
+  if (priv) {
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < nz; i += kThreads)
+      if (sh[i]) atomicAdd(&cnt[i], sh[i]);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_mixed_place(const uint64_t* __restrict__ ukeys,
+                                                          int64_t M, int64_t nz,
+                                                          const uint8_t* __restrict__ sdense,
+                                                          const int64_t* __restrict__ soff,
+                                                          int32_t* __restrict__ stab, uint64_t* hk,
+                                                          int32_t* hv, uint64_t mask) {
+  const int64_t u = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (u >= M) return;
+  const uint64_t g = ukeys[u];
+  const int64_t k = (int64_t)(g % (uint64_t)nz);
+  if (sdense[k])
+    stab[soff[k] + (int64_t)(g / (uint64_t)nz)] = (int32_t)u;
+  else
+    hash_insert(hk, hv, mask, g, (int32_t)u);
+}
+
+// ---------------------------------------------------------------- host side
+static chs_status validate(const double* xyz, int64_t n, const chs_build_params* p,
+                           chs_index* out) {
+  if (!out) {
+    set_error("out is NULL");
+    return CHS_E_INVALID;
+  }
+  if (!xyz || !p) {
+    set_error("xyz or params is NULL");
+    return CHS_E_INVALID;
+  }
+  if (n < 1 || n > (int64_t)INT32_MAX) {
+    set_error("n = %lld outside [1, 2^31 - 1]", (long long)n);
+    return CHS_E_INVALID;
+  }
+  if (p->flavor < CHS_DENSE || p->flavor > CHS_MIXED) {
+    set_error("unknown flavor %d", p->flavor);
+    return CHS_E_INVALID;
+  }
+  if (p->dims != 2 && p->dims != 3) {
+    set_error("dims must be 2 or 3, got %d", p->dims);
+    return CHS_E_INVALID;
+  }
+  for (int a = 0; a < p->dims; ++a)
+    if (!(p->cell[a] > 0.0) || !std::isfinite(p->cell[a])) {
+      set_error("cell[%d] must be finite and > 0", a);
+      return CHS_E_INVALID;
+    }
+  if (p->mixed_dense_pct < 0 || p->mixed_dense_pct > 100) {
+    set_error("mixed_dense_pct must be in [0, 100]");
+    return CHS_E_INVALID;
+  }
+  if (p->reserved != 0 || p->max_dense_cells < 0) {
+    set_error("reserved must be 0 and max_dense_cells >= 0");
+    return CHS_E_INVALID;
+  }
+  return CHS_OK;
+}
+
+template <class K>
+static chs_status build_sorted(chs_index ix, const double* xyz, int64_t n, const KeyArgs& ka,
+                               int bits) {
+  const Alloc& al = ix->al;
+  hipStream_t st = al.stream;
+  Buf keys(&al), vals(&al), tk(&al), tv(&al), xyz4(&al);
+  CHS_TRY(keys.alloc(sizeof(K) * n));
+  CHS_TRY(vals.alloc(sizeof(uint32_t) * n));
+  CHS_TRY(tk.alloc(sizeof(K) * n));
+  CHS_TRY(tv.alloc(sizeof(uint32_t) * n));
+  CHS_TRY(xyz4.alloc(sizeof(float4) * n));
+  k_keys<K><<<grid_for(n), kThreads, 0, st>>>(xyz, n, ka, keys.as<K>(), vals.as<uint32_t>(),
+                                              xyz4.as<float4>());
+  CHS_LAUNCH_CHECK();
+  if (sizeof(K) == 4)
+    CHS_TRY(radix_sort_u32(al, (uint32_t*)keys.p, vals.as<uint32_t>(), (uint32_t*)tk.p,
+                           tv.as<uint32_t>(), n, bits));
+  else
+    CHS_TRY(radix_sort_u64(al, (uint64_t*)keys.p, vals.as<uint32_t>(), (uint64_t*)tk.p,
+                           tv.as<uint32_t>(), n, bits));
+  CHS_TRY(ix->own(&ix->pts, n));
+  CHS_TRY(ix->own(&ix->sxyz, 3 * n));
+  CHS_TRY(ix->own(&ix->perm, n));
+  CHS_TRY(ix->own(&ix->inv_perm, n));
+  k_gather_points<<<grid_for(n), kThreads, 0, st>>>(vals.as<uint32_t>(), xyz4.as<float4>(), n,
+                                                    ix->pts, ix->sxyz, ix->perm, ix->inv_perm);
+  CHS_LAUNCH_CHECK();
+  xyz4.release();
+  tk.release();
+  tv.release();
+  // non-empty voxels: run heads of the sorted keys, compacted by a prefix sum
+  Buf flag(&al), uidx(&al);
+  CHS_TRY(flag.alloc(sizeof(int32_t) * n));
+  CHS_TRY(uidx.alloc(sizeof(int32_t) * (n + 1)));
+  k_run_heads<K><<<grid_for(n), kThreads, 0, st>>>(keys.as<K>(), n, flag.as<int32_t>());
+  CHS_LAUNCH_CHECK();
+  CHS_TRY(exclusive_scan_i32_i32(al, flag.as<int32_t>(), uidx.as<int32_t>(), n));
+  int32_t M = 0;
+  CHS_HIP(hipMemcpyAsync(&M, uidx.as<int32_t>() + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  CHS_HIP(hipStreamSynchronize(st));
+  ix->M = M;
+  CHS_TRY(ix->own(&ix->ukeys, (size_t)M));
+  CHS_TRY(ix->own(&ix->ustart, (size_t)M + 1));
+  k_compact_voxels<K><<<grid_for(n + 1), kThreads, 0, st>>>(keys.as<K>(), flag.as<int32_t>(),
+                                                            uidx.as<int32_t>(), n, ix->ukeys,
+                                                            ix->ustart);
+  CHS_LAUNCH_CHECK();
+  return CHS_OK;
+}
+
+static chs_status build_dense(chs_index ix) {
+  const Alloc& al = ix->al;
+  hipStream_t st = al.stream;
+  const int64_t nc = (int64_t)ix->ncells;
+  Buf cnt(&al);
+  CHS_TRY(cnt.alloc(sizeof(int32_t) * nc));
+  k_fill_i32<<<4096, kThreads, 0, st>>>(cnt.as<int32_t>(), nc, 0);
+  CHS_LAUNCH_CHECK();
+  k_voxel_counts<<<grid_for(ix->M), kThreads, 0, st>>>(ix->ukeys, ix->ustart, ix->M,
+                                                        cnt.as<int32_t>());
+  CHS_LAUNCH_CHECK();
+  CHS_TRY(ix->own(&ix->dstart, (size_t)nc + 1));
+  CHS_TRY(exclusive_scan_i32_i32(al, cnt.as<int32_t>(), ix->dstart, nc));
+  return CHS_OK;
+}
+
+static chs_status alloc_hash(chs_index ix, int64_t nkeys) {
+  uint64_t cap = 64;
+  while (cap < (uint64_t)(2 * nkeys)) cap <<= 1;  // load factor <= 0.5
+  ix->hcap = cap;
+  CHS_TRY(ix->own(&ix->hkeys, cap));
+  CHS_TRY(ix->own(&ix->hvals, cap));
+  k_fill_u64<<<1024, kThreads, 0, ix->al.stream>>>(ix->hkeys, (int64_t)cap, kEmptyKey);
+  CHS_LAUNCH_CHECK();
+  return CHS_OK;
+}
+
+static chs_status build_sparse(chs_index ix) {
+  CHS_TRY(alloc_hash(ix, ix->M));
+  k_hash_build<<<grid_for(ix->M), kThreads, 0, ix->al.stream>>>(ix->ukeys, ix->M, ix->hkeys,
+                                                                 ix->hvals, ix->hcap - 1);
+  CHS_LAUNCH_CHECK();
+  return CHS_OK;
+}
+
+static chs_status build_mixed(chs_index ix) {
+  const Alloc& al = ix->al;
+  hipStream_t st = al.stream;
+  const int64_t nz = ix->ncell[2], nxy = ix->ncell[0] * ix->ncell[1];
+  Buf cnt(&al);
+  CHS_TRY(cnt.alloc(sizeof(int32_t) * nz));
+  k_fill_i32<<<grid_for(nz), kThreads, 0, st>>>(cnt.as<int32_t>(), nz, 0);
+  CHS_LAUNCH_CHECK();
+  const size_t shmem = nz <= 4096 ? sizeof(int32_t) * nz : 0;
+  k_slice_counts<<<256, kThreads, shmem, st>>>(ix->ukeys, ix->M, nz, cnt.as<int32_t>());
+  CHS_LAUNCH_CHECK();
+  std::vector<int32_t> hc(nz);
+  CHS_HIP(hipMemcpyAsync(hc.data(), cnt.p, sizeof(int32_t) * nz, hipMemcpyDeviceToHost, st));
+  CHS_HIP(hipStreamSynchronize(st));
+  std::vector<uint8_t> dense(nz, 0);
+  std::vector<int64_t> off(nz, -1);
+  int64_t ndense = 0, sparse_keys = 0;
+  for (int64_t k = 0; k < nz; ++k) {
+    // Section 3.3.3: a slice turns dense once mixed_dense_pct % of its voxels hold points
+    if (100 * (int64_t)hc[k] >= (int64_t)ix->mixed_pct * nxy) {
+      dense[k] = 1;
+      off[k] = ndense * nxy;
+      ++ndense;
+    } else {
+      sparse_keys += hc[k];
+    }
+  }
+  ix->n_dense_slices = ndense;
+  CHS_TRY(ix->own(&ix->slice_dense, (size_t)nz));
+  CHS_TRY(ix->own(&ix->slice_off, (size_t)nz));
+  CHS_HIP(hipMemcpyAsync(ix->slice_dense, dense.data(), nz, hipMemcpyHostToDevice, st));
+  CHS_HIP(hipMemcpyAsync(ix->slice_off, off.data(), sizeof(int64_t) * nz, hipMemcpyHostToDevice, st));
+  CHS_TRY(ix->own(&ix->stab, (size_t)(ndense * nxy)));
+  if (ndense * nxy > 0) {
+    k_fill_i32<<<4096, kThreads, 0, st>>>(ix->stab, ndense * nxy, -1);
+    CHS_LAUNCH_CHECK();
+  }
+  CHS_TRY(alloc_hash(ix, sparse_keys));
+  k_mixed_place<<<grid_for(ix->M), kThreads, 0, st>>>(ix->ukeys, ix->M, nz, ix->slice_dense,
+                                                       ix->slice_off, ix->stab, ix->hkeys,
+                                                       ix->hvals, ix->hcap - 1);
+  CHS_LAUNCH_CHECK();
+  // the host vectors must outlive the asynchronous copies
+  CHS_HIP(hipStreamSynchronize(st));
+  return CHS_OK;
+}
+
+static chs_status build_impl(chs_index ix, const double* xyz, int64_t n) {
+  const Alloc& al = ix->al;
+  hipStream_t st = al.stream;
+  // Eq. 1-2: bounding box (FP64) and a non-finite check
+  Buf part(&al), bb(&al);
+  CHS_TRY(part.alloc(sizeof(double) * 7 * kBoxBlocks));
+  CHS_TRY(bb.alloc(sizeof(double) * 7));
+  int nb = (int)((n + kThreads - 1) / kThreads);
+  if (nb > kBoxBlocks) nb = kBoxBlocks;
+  k_bbox<<<nb, kThreads, 0, st>>>(xyz, n, part.as<double>());
+  CHS_LAUNCH_CHECK();
+  k_bbox_final<<<1, 64, 0, st>>>(part.as<double>(), nb, bb.as<double>());
+  CHS_LAUNCH_CHECK();
+  double h[7];
+  CHS_HIP(hipMemcpyAsync(h, bb.p, sizeof(h), hipMemcpyDeviceToHost, st));
+  CHS_HIP(hipStreamSynchronize(st));
+  if (h[6] != 0.0) {
+    set_error("xyz holds non-finite coordinates");
+    return CHS_E_INVALID;
+  }
+  for (int a = 0; a < 3; ++a) {
+    ix->origin[a] = h[a];
+    // recentring is monotone, so the FP32 maximum is fl32(max - min)
+    ix->max32[a] = (float)(h[3 + a] - h[a]);
+  }
+  // Eq. 3: n_a = floor((p+_a - p-_a) / s_a) + 1; 2D indexing keeps one z voxel
+  double prod = 1.0;
+  for (int a = 0; a < 3; ++a) {
+    if (a == 2 && ix->dims == 2) {
+      ix->ncell[2] = 1;
+      continue;
+    }
+    const double na = std::floor((double)ix->max32[a] / ix->cell[a]) + 1.0;
+    if (!(na < 4.0e18)) {
+      set_error("grid axis %d would have %g voxels", a, na);
+      return CHS_E_CAPACITY;
+    }
+    ix->ncell[a] = (int64_t)na;
+    prod *= na;
+  }
+  if (!(prod < 9.0e18)) {
+    set_error("grid would have %g voxels (global index overflows 64 bits)", prod);
+    return CHS_E_CAPACITY;
+  }
+  ix->ncells = (uint64_t)ix->ncell[0] * (uint64_t)ix->ncell[1] * (uint64_t)ix->ncell[2];
+  if (ix->flavor == CHS_DENSE) {
+    if (ix->ncells > (uint64_t)ix->ncells_limit()) {
+      set_error("dense grid of %llu voxels exceeds the limit %lld; use the sparse or mixed flavor",
+                (unsigned long long)ix->ncells, (long long)ix->ncells_limit());
+      return CHS_E_CAPACITY;
+    }
+  }
+  if (ix->flavor == CHS_MIXED &&
+      (double)ix->ncell[0] * (double)ix->ncell[1] > 2.0e9) {
+    set_error("mixed flavor: a z-slice of %lld x %lld voxels is too large",
+              (long long)ix->ncell[0], (long long)ix->ncell[1]);
+    return CHS_E_CAPACITY;
+  }
+  KeyArgs ka;
+  for (int a = 0; a < 3; ++a) {
+    ka.origin[a] = ix->origin[a];
+    ka.s[a] = ix->cell[a];
+    ka.n[a] = ix->ncell[a];
+  }
+  ka.dims = ix->dims;
+  const int bits = ceil_log2(ix->ncells);
+  if (bits <= 32)
+    CHS_TRY(build_sorted<uint32_t>(ix, xyz, n, ka, bits));
+  else
+    CHS_TRY(build_sorted<uint64_t>(ix, xyz, n, ka, bits));
+  if (ix->flavor == CHS_DENSE) CHS_TRY(build_dense(ix));
+  if (ix->flavor == CHS_SPARSE) CHS_TRY(build_sparse(ix));
+  if (ix->flavor == CHS_MIXED) CHS_TRY(build_mixed(ix));
+  return CHS_OK;
+}
+
+}  // namespace chs
+
+using namespace chs;
+
+extern "C" chs_status chs_build(const double* xyz, int64_t n, const chs_build_params* params,
+                                const chs_allocator* alloc, hipStream_t stream, chs_index* out) {
+  clear_error();
+  CHS_TRY(validate(xyz, n, params, out));
+  if (alloc && (!alloc->alloc || !alloc->free)) {
+    set_error("allocator callbacks are NULL");
+    return CHS_E_INVALID;
+  }
+  chs_index ix = new chs_index_s();
+  ix->al.stream = stream;
+  if (alloc) {
+    ix->al.a = *alloc;
+    ix->al.has = true;
+  }
+  ix->flavor = params->flavor;
+  ix->dims = params->dims;
+  ix->mixed_pct = params->mixed_dense_pct > 0 ? params->mixed_dense_pct : 80;
+  ix->max_dense = params->max_dense_cells > 0 ? params->max_dense_cells : (int64_t)INT32_MAX - 1;
+  for (int a = 0; a < 3; ++a) ix->cell[a] = params->cell[a];
+  if (ix->dims == 2) ix->cell[2] = 1.0;
+  ix->n = n;
+  if (hipGetDevice(&ix->device) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("no HIP device");
+    delete ix;
+    return CHS_E_DEVICE;
+  }
+  chs_status s = build_impl(ix, xyz, n);
+  if (s != CHS_OK) {
+    std::string msg = last_error();
+    chs_free(ix);
+    set_error("%s", msg.c_str());
+    return s;
+  }
+  *out = ix;
+  return CHS_OK;
+}
+
+extern "C" void chs_free(chs_index ix) {
+  if (!ix) return;
+  for (void* p : ix->owned) ix->al.put(p);
+  ix->owned.clear();
+  delete ix;
+}
+
+extern "C" chs_status chs_index_info(chs_index ix, chs_index_info_t* out) {
+  clear_error();
+  if (!ix || !out) {
+    set_error("index or out is NULL");
+    return CHS_E_INVALID;
+  }
+  std::memset(out, 0, sizeof(*out));
+  for (int a = 0; a < 3; ++a) {
+    out->origin[a] = ix->origin[a];
+    out->max32[a] = ix->max32[a];
+    out->cell[a] = ix->cell[a];
+    out->ncell[a] = ix->ncell[a];
+  }
+  out->n_points = ix->n;
+  out->n_nonempty = ix->M;
+  out->n_dense_slices = ix->n_dense_slices;
+  out->device_bytes = ix->device_bytes;
+  out->flavor = ix->flavor;
+  out->dims = ix->dims;
+  return CHS_OK;
+}
+
+extern "C" chs_status chs_index_arrays(chs_index ix, chs_index_arrays_t* out) {
+  clear_error();
+  if (!ix || !out) {
+    set_error("index or out is NULL");
+    return CHS_E_INVALID;
+  }
+  out->perm = ix->perm;
+  out->inv_perm = ix->inv_perm;
+  out->sorted_xyz = ix->sxyz;
+  out->points = reinterpret_cast<const float*>(ix->pts);
+  out->cell_keys = ix->ukeys;
+  out->cell_start = ix->ustart;
+  out->dense_start = ix->flavor == CHS_DENSE ? ix->dstart : nullptr;
+  out->slice_dense = ix->flavor == CHS_MIXED ? ix->slice_dense : nullptr;
+  return CHS_OK;
+}

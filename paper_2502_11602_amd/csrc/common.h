@@ -1,0 +1,343 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/chs.h"
+
+#pragma clang fp contract(off)
+
+namespace chs {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+void clear_error();
+const char* last_error();
+
+#define CHS_HIP(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess) {                                                            \
+      ::chs::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, \
+                       __LINE__);                                                      \
+      return CHS_E_DEVICE;                                                             \
+    }                                                                                  \
+  } while (0)
+
+#define CHS_TRY(expr)                 \
+  do {                                \
+    chs_status _s = (expr);           \
+    if (_s != CHS_OK) return _s;      \
+  } while (0)
+
+#define CHS_LAUNCH_CHECK() CHS_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------- memory
+// Device memory through the caller's allocator, or stream-ordered
+// hipMallocAsync when none is given.
+struct Alloc {
+  chs_allocator a{};
+  bool has = false;
+  hipStream_t stream = nullptr;
+  void* get(size_t bytes) const;
+  void put(void* p) const;
+};
+
+// A temporary device buffer released when it goes out of scope.
+struct Buf {
+  const Alloc* al = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  Buf() = default;
+  explicit Buf(const Alloc* a) : al(a) {}
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+  ~Buf() { release(); }
+  chs_status alloc(size_t nbytes);
+  void release() {
+    if (p && al) al->put(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------- grid
+// Grid geometry as the kernels see it.
+struct Grid {
+  double s[3];   // voxel edges
+  int64_t n[3];  // n_x, n_y, n_z
+  int32_t dims;
+};
+
+// Voxel storage as the kernels see it.
+struct Voxels {
+  int32_t flavor;
+  const int32_t* dstart;     // DENSE: [ncells+1]
+  const uint64_t* hkeys;     // SPARSE/MIXED: open-addressing keys (EMPTY = ~0)
+  const int32_t* hvals;      //   -> compact voxel id
+  uint64_t hmask;            //   capacity - 1 (power of two)
+  const int32_t* ustart;     // compact voxel id -> first stored position, [M+1]
+  const uint8_t* slice_dense;  // MIXED: [n_z]
+  const int64_t* slice_off;    // MIXED: [n_z] offset of a dense slice's table
+  const int32_t* stab;         // MIXED: dense slice tables, compact id or -1
+};
+
+constexpr uint64_t kEmptyKey = ~0ull;
+
+}  // namespace chs
+
+struct chs_index_s {
+  chs::Alloc al;
+  int device = 0;
+  int32_t flavor = 0, dims = 3, mixed_pct = 80;
+  double cell[3] = {1, 1, 1};
+  double origin[3] = {0, 0, 0};
+  float max32[3] = {0, 0, 0};
+  int64_t ncell[3] = {1, 1, 1};
+  uint64_t ncells = 1;
+  int64_t n = 0, M = 0;
+  int64_t n_dense_slices = 0;
+  int64_t device_bytes = 0;
+  int64_t max_dense = (int64_t)INT32_MAX - 1;
+  int64_t ncells_limit() const { return max_dense; }
+  // stored (voxel-ordered) cloud
+  int32_t* perm = nullptr;
+  int32_t* inv_perm = nullptr;
+  float* sxyz = nullptr;      // SoA [3][n]
+  float4* pts = nullptr;      // [n] x, y, z, original index bits
+  uint64_t* ukeys = nullptr;  // [M]
+  int32_t* ustart = nullptr;  // [M+1]
+  // flavor maps
+  int32_t* dstart = nullptr;
+  uint64_t* hkeys = nullptr;
+  int32_t* hvals = nullptr;
+  uint64_t hcap = 0;
+  uint8_t* slice_dense = nullptr;
+  int64_t* slice_off = nullptr;
+  int32_t* stab = nullptr;
+  // cached processing order for "every point" queries
+  float4* allq = nullptr;
+  std::vector<void*> owned;
+
+  chs::Grid grid() const {
+    chs::Grid g;
+    for (int a = 0; a < 3; ++a) {
+      g.s[a] = cell[a];
+      g.n[a] = ncell[a];
+    }
+    g.dims = dims;
+    return g;
+  }
+  chs::Voxels voxels() const {
+    chs::Voxels v;
+    v.flavor = flavor;
+    v.dstart = dstart;
+    v.hkeys = hkeys;
+    v.hvals = hvals;
+    v.hmask = hcap ? hcap - 1 : 0;
+    v.ustart = ustart;
+    v.slice_dense = slice_dense;
+    v.slice_off = slice_off;
+    v.stab = stab;
+    return v;
+  }
+  // index-owned allocation
+  template <class T>
+  chs_status own(T** out, size_t count) {
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = 256;
+    void* p = al.get(bytes);
+    if (!p) {
+      chs::set_error("allocator returned NULL for %zu bytes", bytes);
+      return CHS_E_NOMEM;
+    }
+    owned.push_back(p);
+    device_bytes += (int64_t)bytes;
+    *out = static_cast<T*>(p);
+    return CHS_OK;
+  }
+};
+
+namespace chs {
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+template <class T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    T o = __shfl_xor(v, m, kWave);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    T o = __shfl_xor(v, m, kWave);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Voxel coordinate along one axis: floor of the IEEE FP64 quotient, as a
+// double (may be negative or beyond the grid for query boxes).
+__device__ __forceinline__ double vfloor(double v, double s) { return floor(v / s); }
+
+// Same, clamped into the grid (0-based, Eq. 5).
+__device__ __forceinline__ int64_t voxel_clamped(double v, double s, int64_t n) {
+  double c = floor(v / s);
+  if (c > (double)(n - 1)) return n - 1;
+  if (c < 0.0) return 0;
+  return (int64_t)c;
+}
+
+// splitmix64 finaliser, used to spread voxel keys over the hash table.
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ull;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebull;
+  x ^= x >> 31;
+  return x;
+}
+
+// Compact id of voxel g in the hash map, or -1 when the voxel is not stored.
+__device__ __forceinline__ int32_t hash_find(const uint64_t* __restrict__ hk,
+                                             const int32_t* __restrict__ hv, uint64_t mask,
+                                             uint64_t g) {
+  uint64_t h = mix64(g) & mask;
+  while (true) {
+    uint64_t k = hk[h];
+    if (k == g) return hv[h];
+    if (k == kEmptyKey) return -1;
+    h = (h + 1) & mask;
+  }
+}
+
+// Compact id of the non-empty voxel (i,j,k), or -1 if it holds no point.
+__device__ __forceinline__ int32_t voxel_id(const Voxels& vx, const Grid& g, int64_t i, int64_t j,
+                                            int64_t k) {
+  const uint64_t key = ((uint64_t)i * (uint64_t)g.n[1] + (uint64_t)j) * (uint64_t)g.n[2] + (uint64_t)k;
+  if (vx.flavor == CHS_MIXED && vx.slice_dense[k])
+    return vx.stab[vx.slice_off[k] + i * g.n[1] + j];
+  return hash_find(vx.hkeys, vx.hvals, vx.hmask, key);
+}
+
+// Stored-position range [b, e) of the voxels (i, j, k0..k1) of one column.
+// Because the global index is z-fastest (Eq. 7), these voxels are adjacent
+// in the stored order and their points form one contiguous run.
+__device__ __forceinline__ void column_run(const Voxels& vx, const Grid& g, int64_t i, int64_t j,
+                                           int64_t k0, int64_t k1, int32_t* b, int32_t* e) {
+  const uint64_t base = ((uint64_t)i * (uint64_t)g.n[1] + (uint64_t)j) * (uint64_t)g.n[2];
+  if (vx.flavor == CHS_DENSE) {
+    *b = vx.dstart[base + k0];
+    *e = vx.dstart[base + k1 + 1];
+    return;
+  }
+  int64_t k = k0;
+  int32_t u0 = -1;
+  for (; k <= k1; ++k) {
+    u0 = voxel_id(vx, g, i, j, k);
+    if (u0 >= 0) break;
+  }
+  if (u0 < 0) {
+    *b = 0;
+    *e = 0;
+    return;
+  }
+  int32_t u1 = u0;
+  for (int64_t kk = k1; kk > k; --kk) {
+    int32_t u = voxel_id(vx, g, i, j, kk);
+    if (u >= 0) {
+      u1 = u;
+      break;
+    }
+  }
+  *b = vx.ustart[u0];
+  *e = vx.ustart[u1 + 1];
+}
+
+// Block index remapped so that consecutive logical blocks run on the same
+// XCD (the hardware deals blocks round-robin over the 8 XCDs, each with its
+// own L2): spatially adjacent query tiles then share an L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  constexpr uint32_t X = 8;
+  const uint32_t per = nb / X, rem = nb % X;
+  const uint32_t x = b % X, i = b / X;
+  // XCD x owns logical blocks [x*per + min(x, rem), ...)
+  return x * per + (x < rem ? x : rem) + i;
+}
+
+// ---------------------------------------------------------------- primitives
+// Exclusive prefix sum of n values into out[0..n], out[n] = total.
+chs_status exclusive_scan_i32_i32(const Alloc& al, const int32_t* in, int32_t* out, int64_t n);
+chs_status exclusive_scan_i32_i64(const Alloc& al, const int32_t* in, int64_t* out, int64_t n);
+
+// Stable LSD radix sort of (key, value) pairs on bits [0, bits).  The result
+// ends in (keys, vals); (tk, tv) are scratch of the same size.
+chs_status radix_sort_u32(const Alloc& al, uint32_t* keys, uint32_t* vals, uint32_t* tk,
+                          uint32_t* tv, int64_t n, int bits);
+chs_status radix_sort_u64(const Alloc& al, uint64_t* keys, uint32_t* vals, uint64_t* tk,
+                          uint32_t* tv, int64_t n, int bits);
+
+// Hilbert index of (x, y) on a 2^m x 2^m grid.
+__device__ __forceinline__ uint64_t hilbert2(uint32_t x, uint32_t y, int m) {
+  uint64_t d = 0;
+  for (int b = m - 1; b >= 0; --b) {
+    const uint32_t s = 1u << b;
+    const uint32_t rx = (x & s) ? 1u : 0u;
+    const uint32_t ry = (y & s) ? 1u : 0u;
+    d += (uint64_t)s * s * ((3u * rx) ^ ry);
+    if (ry == 0) {
+      if (rx == 1) {
+        x = s - 1 - (x & (s - 1));
+        y = s - 1 - (y & (s - 1));
+      } else {
+        x &= s - 1;
+        y &= s - 1;
+      }
+      uint32_t t = x;
+      x = y;
+      y = t;
+    } else {
+      x &= s - 1;
+      y &= s - 1;
+    }
+  }
+  return d;
+}
+
+// Processing order of a query batch: centres as float4 (x, y, z recentred
+// FP32, caller index in w), sorted along a Hilbert curve over the (i, j)
+// columns so that 64 consecutive queries are spatial neighbours.
+struct QueryPlan {
+  Buf q4;
+  const float4* q = nullptr;
+  int64_t nq = 0;
+  explicit QueryPlan(const Alloc* al) : q4(al) {}
+};
+chs_status plan_queries(chs_index ix, const chs_queries* qs, QueryPlan* plan, hipStream_t stream);
+
+int ceil_log2(uint64_t v);
+
+}  // namespace chs

@@ -1,0 +1,632 @@
+// Neighbour search on the GPU: fixed-radius (the kernel-based search of
+// Section 3.4.1, Alg. 1, with a spherical kernel) and k-NN (Section 3.4.2,
+// with the taboo box of Section 3.5 as a ring expansion over voxels).
+//
+// Work decomposition: a wavefront owns a tile of 64 consecutive queries in
+// a Hilbert order over the (i, j) voxel columns, so its queries are spatial
+// neighbours.  The tile's voxel box (the union of its queries' kernel boxes)
+// is enumerated column by column, one column per lane; every column's voxels
+// k0..k1 are contiguous in the stored order (the global index is z-fastest,
+// Eq. 7), so each column yields one run of candidate points.  The wave then
+// walks the runs with wave-uniform indices, so every candidate point is
+// fetched once per wave through the scalar unit and compared against the 64
+// queries held in the lanes: no per-lane gathers, no LDS, and the distance
+// arithmetic is the unfused FP32 definition.
+#include <cmath>
+
+#include "common.h"
+
+#pragma clang fp contract(off)
+
+namespace chs {
+
+constexpr int kThreads = 256;
+constexpr int kWavesPerBlock = kThreads / kWave;
+constexpr uint32_t kInactive = 0x80000000u;
+constexpr double kPadRel = 1.0 / 262144.0;              // 2^-18
+constexpr double kPadAbs = 8.673617379884035e-19;       // 2^-60
+
+static unsigned grid_for(int64_t n, int per_block = kThreads) {
+  int64_t b = (n + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+// ---------------------------------------------------------------- query planning
+struct PlanArgs {
+  double origin[3];
+  Grid g;
+  int m;       // Hilbert order (bits per axis)
+  int kbits;   // bits of the z voxel index
+};
+
+// Per query: recentred FP32 centre (invalid queries are flagged) and the
+// ordering key hilbert(i, j) << kbits | k.
+template <class K>
+__global__ __launch_bounds__(kThreads) void k_plan_keys(
+    int mode, const double* __restrict__ xyz, const int32_t* __restrict__ pidx, int64_t nq,
+    const float4* __restrict__ pts, const int32_t* __restrict__ inv_perm,
+    const int32_t* __restrict__ perm, int64_t npts, PlanArgs pa, K* __restrict__ keys,
+    uint32_t* __restrict__ vals, float4* __restrict__ tmp) {
+  const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (q >= nq) return;
+  float4 c;
+  bool ok = true;
+  uint32_t caller = (uint32_t)q;
+  if (mode == 0) {  // every point, walked in stored order
+    c = pts[q];
+    caller = (uint32_t)perm[q];
+  } else if (mode == 1) {  // point indices
+    const int32_t p = pidx[q];
+    ok = p >= 0 && (int64_t)p < npts;
+    c = ok ? pts[inv_perm[p]] : make_float4(0.f, 0.f, 0.f, 0.f);
+  } else {  // FP64 coordinates
+    float v[3];
+    for (int a = 0; a < 3; ++a) {
+      const double x = xyz[q * 3 + a];
+      ok = ok && isfinite(x);
+      v[a] = (float)(x - pa.origin[a]);
+    }
+    if (!ok) v[0] = v[1] = v[2] = 0.f;
+    c = make_float4(v[0], v[1], v[2], 0.f);
+  }
+  int64_t cell[3] = {0, 0, 0};
+  const float cc[3] = {c.x, c.y, c.z};
+  for (int a = 0; a < pa.g.dims; ++a) cell[a] = voxel_clamped((double)cc[a], pa.g.s[a], pa.g.n[a]);
+  const int total = 2 * pa.m + pa.kbits;
+  K key;
+  if (ok) {
+    key = (K)((hilbert2((uint32_t)cell[0], (uint32_t)cell[1], pa.m) << pa.kbits) | (uint64_t)cell[2]);
+  } else {
+    key = (K)(total >= 64 ? ~0ull : ((1ull << total) - 1));
+  }
+  keys[q] = key;
+  vals[q] = (uint32_t)q;
+  c.w = __uint_as_float(ok ? caller : (caller | kInactive));
+  tmp[q] = c;
+}
+
+__global__ __launch_bounds__(kThreads) void k_plan_gather(const uint32_t* __restrict__ order,
+                                                          const float4* __restrict__ tmp,
+                                                          int64_t nq, float4* __restrict__ q4) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= nq) return;
+  q4[t] = tmp[order[t]];
+}
+
+static chs_status plan_impl(chs_index ix, int mode, const double* xyz, const int32_t* pidx,
+                            int64_t nq, float4* q4, hipStream_t st) {
+  Alloc al = ix->al;
+  al.stream = st;
+  PlanArgs pa;
+  for (int a = 0; a < 3; ++a) pa.origin[a] = ix->origin[a];
+  pa.g = ix->grid();
+  int64_t nmax = ix->ncell[0] > ix->ncell[1] ? ix->ncell[0] : ix->ncell[1];
+  pa.m = ceil_log2((uint64_t)nmax);
+  pa.kbits = ceil_log2((uint64_t)ix->ncell[2]);
+  const int bits = 2 * pa.m + pa.kbits;
+  Buf keys(&al), vals(&al), tk(&al), tv(&al), tmp(&al);
+  const bool wide = bits > 32;
+  const size_t ks = wide ? 8 : 4;
+  CHS_TRY(keys.alloc(ks * nq));
+  CHS_TRY(tk.alloc(ks * nq));
+  CHS_TRY(vals.alloc(4 * nq));
+  CHS_TRY(tv.alloc(4 * nq));
+  CHS_TRY(tmp.alloc(sizeof(float4) * nq));
+  if (wide) {
+    k_plan_keys<uint64_t><<<grid_for(nq), kThreads, 0, st>>>(
+        mode, xyz, pidx, nq, ix->pts, ix->inv_perm, ix->perm, ix->n, pa, keys.as<uint64_t>(),
+        vals.as<uint32_t>(), tmp.as<float4>());
+    CHS_LAUNCH_CHECK();
+    CHS_TRY(radix_sort_u64(al, keys.as<uint64_t>(), vals.as<uint32_t>(), tk.as<uint64_t>(),
+                           tv.as<uint32_t>(), nq, bits));
+  } else {
+    k_plan_keys<uint32_t><<<grid_for(nq), kThreads, 0, st>>>(
+        mode, xyz, pidx, nq, ix->pts, ix->inv_perm, ix->perm, ix->n, pa, keys.as<uint32_t>(),
+        vals.as<uint32_t>(), tmp.as<float4>());
+    CHS_LAUNCH_CHECK();
+    CHS_TRY(radix_sort_u32(al, keys.as<uint32_t>(), vals.as<uint32_t>(), tk.as<uint32_t>(),
+                           tv.as<uint32_t>(), nq, bits));
+  }
+  k_plan_gather<<<grid_for(nq), kThreads, 0, st>>>(vals.as<uint32_t>(), tmp.as<float4>(), nq, q4);
+  CHS_LAUNCH_CHECK();
+  return CHS_OK;
+}
+
+static chs_status check_queries(chs_index ix, const chs_queries* qs) {
+  if (!ix || !qs) {
+    set_error("index or queries is NULL");
+    return CHS_E_INVALID;
+  }
+  if (qs->xyz && qs->point_idx) {
+    set_error("queries: give xyz or point_idx, not both");
+    return CHS_E_INVALID;
+  }
+  if (qs->nq < 0 || qs->nq > (int64_t)INT32_MAX) {
+    set_error("queries: nq = %lld outside [0, 2^31 - 1]", (long long)qs->nq);
+    return CHS_E_INVALID;
+  }
+  if (!qs->xyz && !qs->point_idx && qs->nq != 0 && qs->nq != ix->n) {
+    set_error("queries: with neither xyz nor point_idx, nq must equal the cloud size %lld",
+              (long long)ix->n);
+    return CHS_E_INVALID;
+  }
+  return CHS_OK;
+}
+
+chs_status plan_queries(chs_index ix, const chs_queries* qs, QueryPlan* plan, hipStream_t st) {
+  plan->nq = qs->nq;
+  if (qs->nq == 0) return CHS_OK;
+  if (!qs->xyz && !qs->point_idx) {
+    if (!ix->allq) {
+      // cached on the index: the order of "every point" queries never changes
+      Alloc al = ix->al;
+      float4* a = nullptr;
+      CHS_TRY(ix->own(&a, (size_t)ix->n));
+      chs_status s = plan_impl(ix, 0, nullptr, nullptr, ix->n, a, st);
+      if (s != CHS_OK) return s;
+      ix->allq = a;
+      (void)al;
+    }
+    plan->q = ix->allq;
+    return CHS_OK;
+  }
+  CHS_TRY(plan->q4.alloc(sizeof(float4) * qs->nq));
+  CHS_TRY(plan_impl(ix, qs->point_idx ? 1 : 2, qs->xyz, qs->point_idx, qs->nq,
+                    plan->q4.as<float4>(), st));
+  plan->q = plan->q4.as<float4>();
+  return CHS_OK;
+}
+
+// ---------------------------------------------------------------- tile geometry
+struct Tile {
+  bool any;             // at least one active lane
+  float lo[3], hi[3];   // bounding box of the active queries
+};
+
+__device__ __forceinline__ Tile tile_bounds(float4 q, bool active) {
+  Tile t;
+  const float inf = INFINITY;
+  t.lo[0] = wave_min(active ? q.x : inf);
+  t.lo[1] = wave_min(active ? q.y : inf);
+  t.lo[2] = wave_min(active ? q.z : inf);
+  t.hi[0] = wave_max(active ? q.x : -inf);
+  t.hi[1] = wave_max(active ? q.y : -inf);
+  t.hi[2] = wave_max(active ? q.z : -inf);
+  t.any = __ballot(active) != 0ull;
+  return t;
+}
+
+struct VBox {
+  int64_t lo[3], hi[3];
+  bool empty;
+};
+
+// Voxel box covering [lo - pad, hi + pad] along every indexed axis, clamped
+// to the grid; empty when it misses the grid.
+__device__ __forceinline__ VBox voxel_box(const Grid& g, const float* lo, const float* hi,
+                                          double pad) {
+  VBox b;
+  b.empty = false;
+  for (int a = 0; a < 3; ++a) {
+    if (a >= g.dims) {
+      b.lo[a] = 0;
+      b.hi[a] = 0;
+      continue;
+    }
+    const double clo = floor(((double)lo[a] - pad) / g.s[a]);
+    const double chi = floor(((double)hi[a] + pad) / g.s[a]);
+    if (chi < 0.0 || clo > (double)(g.n[a] - 1)) {
+      b.empty = true;
+      b.lo[a] = 0;
+      b.hi[a] = -1;
+      continue;
+    }
+    b.lo[a] = clo < 0.0 ? 0 : (int64_t)clo;
+    b.hi[a] = chi > (double)(g.n[a] - 1) ? g.n[a] - 1 : (int64_t)chi;
+  }
+  return b;
+}
+
+// Lower bound of the horizontal distance between the tile's query box and
+// column (i, j); columns farther than the search radius are skipped.  The
+// column's extent is widened by a relative 1e-9 so that the FP64 rounding of
+// the voxel function can never make this test drop a candidate.
+__device__ __forceinline__ bool column_near(const Grid& g, const Tile& t, int64_t i, int64_t j,
+                                            double pad) {
+  const double x0 = (double)i * g.s[0], x1 = (double)(i + 1) * g.s[0];
+  const double y0 = (double)j * g.s[1], y1 = (double)(j + 1) * g.s[1];
+  const double ex = 1e-9 * (fabs(x1) + g.s[0]), ey = 1e-9 * (fabs(y1) + g.s[1]);
+  double dx = fmax(0.0, fmax((x0 - ex) - (double)t.hi[0], (double)t.lo[0] - (x1 + ex)));
+  double dy = fmax(0.0, fmax((y0 - ey) - (double)t.hi[1], (double)t.lo[1] - (y1 + ey)));
+  return dx * dx + dy * dy <= pad * pad;
+}
+
+// ---------------------------------------------------------------- radius search
+struct RadiusArgs {
+  const float4* __restrict__ q4;
+  int64_t nq;
+  const float4* __restrict__ pts;
+  Grid g;
+  Voxels vx;
+  float r;
+  int32_t* __restrict__ counts;         // count pass: [nq] caller order
+  const int64_t* __restrict__ offsets;  // fill pass: [nq+1]
+  int32_t* __restrict__ nbr;            // fill pass
+};
+
+template <bool FILL>
+__global__ __launch_bounds__(kThreads) void k_radius(RadiusArgs A) {
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t t0 = ((int64_t)blk * kWavesPerBlock + w) * kWave;
+  if (t0 >= A.nq) return;
+  const int64_t t = t0 + lane;
+  const bool in = t < A.nq;
+  const float4 q = in ? A.q4[t] : make_float4(0.f, 0.f, 0.f, __uint_as_float(kInactive));
+  const uint32_t wq = __float_as_uint(q.w);
+  const bool active = in && !(wq & kInactive);
+  const uint32_t qid = wq & ~kInactive;
+  const Tile tb = tile_bounds(q, active);
+  const float R = A.r * A.r;  // fl32(r*r)
+  const double pad = fmax((double)A.r * (1.0 + kPadRel), kPadAbs);
+  int32_t cnt = 0;
+  int64_t obase = 0;
+  if (FILL && active) obase = A.offsets[qid];
+  if (tb.any) {
+    const VBox bx = voxel_box(A.g, tb.lo, tb.hi, pad);
+    if (!bx.empty) {
+      const int64_t nj = bx.hi[1] - bx.lo[1] + 1;
+      const int64_t ncol = (bx.hi[0] - bx.lo[0] + 1) * nj;
+      for (int64_t cb = 0; cb < ncol; cb += kWave) {
+        const int64_t c = cb + lane;
+        int32_t b = 0, e = 0;
+        if (c < ncol) {
+          const int64_t ci = bx.lo[0] + c / nj, cj = bx.lo[1] + c % nj;
+          if (column_near(A.g, tb, ci, cj, pad)) column_run(A.vx, A.g, ci, cj, bx.lo[2], bx.hi[2], &b, &e);
+        }
+        uint64_t m = __ballot(e > b);
+        while (m) {
+          const int src = __builtin_ctzll(m);
+          m &= m - 1;
+          const int32_t rb = __builtin_amdgcn_readlane(b, src);
+          const int32_t re = __builtin_amdgcn_readlane(e, src);
+#pragma unroll 4
+          for (int32_t p = rb; p < re; ++p) {
+            const float4 P = A.pts[p];
+            const float dx = q.x - P.x, dy = q.y - P.y, dz = q.z - P.z;
+            const float D = (dx * dx + dy * dy) + dz * dz;
+            if (D <= R) {
+              if (FILL) A.nbr[obase + cnt] = __float_as_int(P.w);
+              ++cnt;
+            }
+          }
+        }
+      }
+    }
+  }
+  if (!FILL && in) A.counts[qid] = active ? cnt : 0;
+}
+
+// ---------------------------------------------------------------- k-NN
+struct KnnArgs {
+  const float4* __restrict__ q4;
+  int64_t nq;
+  const float4* __restrict__ pts;
+  Grid g;
+  Voxels vx;
+  int32_t k;
+  float rmax2;  // fl32(r_max^2), +inf without a radius cap
+  int32_t* __restrict__ idx;
+  float* __restrict__ d2;
+};
+
+// Sorted insertion of key x into best[0..KC) (ascending), dropping the last:
+// best'[i] = max(best[i-1], min(x, best[i])).
+template <int KC>
+__device__ __forceinline__ void topk_insert(uint64_t (&best)[KC], uint64_t x) {
+#pragma unroll
+  for (int i = KC - 1; i > 0; --i) {
+    const uint64_t lo = x < best[i] ? x : best[i];
+    best[i] = best[i - 1] > lo ? best[i - 1] : lo;
+  }
+  best[0] = x < best[0] ? x : best[0];
+}
+
+template <int KC>
+__device__ __forceinline__ void scan_run(const float4* __restrict__ pts, int32_t rb, int32_t re,
+                                         float4 q, float rmax2, uint64_t (&best)[KC]) {
+#pragma unroll 2
+  for (int32_t p = rb; p < re; ++p) {
+    const float4 P = pts[p];
+    const float dx = q.x - P.x, dy = q.y - P.y, dz = q.z - P.z;
+    const float D = (dx * dx + dy * dy) + dz * dz;
+    // D >= 0, so its bit pattern orders like its value; ties go to the
+    // lower original index in the low word
+    const uint64_t key = ((uint64_t)__float_as_uint(D) << 32) | (uint64_t)__float_as_uint(P.w);
+    if (D <= rmax2 && key < best[KC - 1]) topk_insert<KC>(best, key);
+  }
+}
+
+template <int KC>
+__global__ __launch_bounds__(kThreads) void k_knn(KnnArgs A) {
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t t0 = ((int64_t)blk * kWavesPerBlock + w) * kWave;
+  if (t0 >= A.nq) return;
+  const int64_t t = t0 + lane;
+  const bool in = t < A.nq;
+  const float4 q = in ? A.q4[t] : make_float4(0.f, 0.f, 0.f, __uint_as_float(kInactive));
+  const uint32_t wq = __float_as_uint(q.w);
+  const bool active = in && !(wq & kInactive);
+  const uint32_t qid = wq & ~kInactive;
+  const Tile tb = tile_bounds(q, active);
+  uint64_t best[KC];
+#pragma unroll
+  for (int i = 0; i < KC; ++i) best[i] = ~0ull;
+  if (tb.any) {
+    const Grid& g = A.g;
+    // ring 0: the voxels holding the tile's queries (clamped into the grid)
+    VBox B;
+    B.empty = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (a >= g.dims) {
+        B.lo[a] = B.hi[a] = 0;
+        continue;
+      }
+      B.lo[a] = voxel_clamped((double)tb.lo[a], g.s[a], g.n[a]);
+      B.hi[a] = voxel_clamped((double)tb.hi[a], g.s[a], g.n[a]);
+    }
+    VBox V;  // visited voxels (the taboo box)
+    V.empty = true;
+    const float qc[3] = {q.x, q.y, q.z};
+    while (true) {
+      // visit B minus V, column by column (one column per lane)
+      const int64_t nj = B.hi[1] - B.lo[1] + 1;
+      const int64_t ncol = (B.hi[0] - B.lo[0] + 1) * nj;
+      for (int64_t cb = 0; cb < ncol; cb += kWave) {
+        const int64_t c = cb + lane;
+        int32_t b0 = 0, e0 = 0, b1 = 0, e1 = 0;
+        if (c < ncol) {
+          const int64_t ci = B.lo[0] + c / nj, cj = B.lo[1] + c % nj;
+          const bool inner = !V.empty && ci >= V.lo[0] && ci <= V.hi[0] && cj >= V.lo[1] &&
+                             cj <= V.hi[1];
+          if (!inner) {
+            column_run(A.vx, g, ci, cj, B.lo[2], B.hi[2], &b0, &e0);
+          } else {
+            if (B.lo[2] < V.lo[2]) column_run(A.vx, g, ci, cj, B.lo[2], V.lo[2] - 1, &b0, &e0);
+            if (B.hi[2] > V.hi[2]) column_run(A.vx, g, ci, cj, V.hi[2] + 1, B.hi[2], &b1, &e1);
+          }
+        }
+        uint64_t m0 = __ballot(e0 > b0);
+        while (m0) {
+          const int src = __builtin_ctzll(m0);
+          m0 &= m0 - 1;
+          scan_run<KC>(A.pts, __builtin_amdgcn_readlane(b0, src), __builtin_amdgcn_readlane(e0, src),
+                       q, A.rmax2, best);
+        }
+        uint64_t m1 = __ballot(e1 > b1);
+        while (m1) {
+          const int src = __builtin_ctzll(m1);
+          m1 &= m1 - 1;
+          scan_run<KC>(A.pts, __builtin_amdgcn_readlane(b1, src), __builtin_amdgcn_readlane(e1, src),
+                       q, A.rmax2, best);
+        }
+      }
+      V = B;
+      // termination: every point outside V lies beyond the nearest face of V
+      // that is not on the grid boundary; once the k-th best (or the radius
+      // cap) is strictly below that distance squared, nothing outside V can
+      // enter the list (ties included).
+      uint64_t kth = best[0];
+#pragma unroll
+      for (int i = 1; i < KC; ++i)
+        if (i == A.k - 1) kth = best[i];
+      float thr = A.rmax2;
+      if (kth != ~0ull) {
+        const float dk = __uint_as_float((uint32_t)(kth >> 32));
+        thr = dk < thr ? dk : thr;
+      }
+      double lb = INFINITY;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (a >= g.dims) continue;
+        const double c = (double)qc[a];
+        if (V.lo[a] > 0) {
+          const double f = (double)V.lo[a] * g.s[a];
+          lb = fmin(lb, (c - f) - 0x1p-50 * (fabs(c) + fabs(f)));
+        }
+        if (V.hi[a] < g.n[a] - 1) {
+          const double f = (double)(V.hi[a] + 1) * g.s[a];
+          lb = fmin(lb, (f - c) - 0x1p-50 * (fabs(c) + fabs(f)));
+        }
+      }
+      if (lb == INFINITY) break;  // V is the whole grid
+      lb = fmax(lb, 0.0);
+      const double lb2 = lb * lb;
+      const bool done = !active || (lb2 >= 0x1p-100 && (double)thr < lb2 * (1.0 - kPadRel));
+      if (__ballot(!done) == 0ull) break;
+      // next ring: grow the box by one voxel on every side
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (a >= g.dims) continue;
+        B.lo[a] = V.lo[a] > 0 ? V.lo[a] - 1 : 0;
+        B.hi[a] = V.hi[a] < g.n[a] - 1 ? V.hi[a] + 1 : g.n[a] - 1;
+      }
+    }
+  }
+  if (in) {
+    int32_t* ro = A.idx + (int64_t)qid * A.k;
+    float* rd = A.d2 + (int64_t)qid * A.k;
+#pragma unroll
+    for (int i = 0; i < KC; ++i) {
+      if (i < A.k) {
+        const uint64_t key = active ? best[i] : ~0ull;
+        const bool ok = key != ~0ull;
+        ro[i] = ok ? (int32_t)(uint32_t)key : -1;
+        rd[i] = ok ? __uint_as_float((uint32_t)(key >> 32)) : INFINITY;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- host side
+static chs_status radius_count_impl(chs_index ix, const QueryPlan& plan, float r, int64_t* offsets,
+                                    hipStream_t st) {
+  Alloc al = ix->al;
+  al.stream = st;
+  const int64_t nq = plan.nq;
+  Buf counts(&al);
+  CHS_TRY(counts.alloc(sizeof(int32_t) * (nq > 0 ? nq : 1)));
+  if (nq > 0) {
+    RadiusArgs A{plan.q, nq, ix->pts, ix->grid(), ix->voxels(), r, counts.as<int32_t>(), nullptr,
+                 nullptr};
+    k_radius<false><<<grid_for(nq), kThreads, 0, st>>>(A);
+    CHS_LAUNCH_CHECK();
+  }
+  CHS_TRY(exclusive_scan_i32_i64(al, counts.as<int32_t>(), offsets, nq));
+  return CHS_OK;
+}
+
+static chs_status radius_fill_impl(chs_index ix, const QueryPlan& plan, float r,
+                                   const int64_t* offsets, int32_t* nbr, hipStream_t st) {
+  const int64_t nq = plan.nq;
+  if (nq == 0) return CHS_OK;
+  RadiusArgs A{plan.q, nq, ix->pts, ix->grid(), ix->voxels(), r, nullptr, offsets, nbr};
+  k_radius<true><<<grid_for(nq), kThreads, 0, st>>>(A);
+  CHS_LAUNCH_CHECK();
+  return CHS_OK;
+}
+
+static chs_status check_r(float r) {
+  if (!(r >= 0.0f) || !std::isfinite(r)) {
+    set_error("radius must be finite and >= 0");
+    return CHS_E_INVALID;
+  }
+  return CHS_OK;
+}
+
+}  // namespace chs
+
+using namespace chs;
+
+extern "C" chs_status chs_radius_count(chs_index ix, const chs_queries* qs, float r,
+                                       int64_t* offsets, int64_t* total, hipStream_t st) {
+  clear_error();
+  CHS_TRY(check_queries(ix, qs));
+  CHS_TRY(check_r(r));
+  if (!offsets || !total) {
+    set_error("offsets or total is NULL");
+    return CHS_E_INVALID;
+  }
+  Alloc al = ix->al;
+  al.stream = st;
+  QueryPlan plan(&al);
+  CHS_TRY(plan_queries(ix, qs, &plan, st));
+  CHS_TRY(radius_count_impl(ix, plan, r, offsets, st));
+  int64_t tot = 0;
+  CHS_HIP(hipMemcpyAsync(&tot, offsets + qs->nq, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  CHS_HIP(hipStreamSynchronize(st));
+  *total = tot;
+  return CHS_OK;
+}
+
+extern "C" chs_status chs_radius_fill(chs_index ix, const chs_queries* qs, float r,
+                                      const int64_t* offsets, int32_t* nbr, int64_t total,
+                                      hipStream_t st) {
+  clear_error();
+  CHS_TRY(check_queries(ix, qs));
+  CHS_TRY(check_r(r));
+  if (!offsets || (total > 0 && !nbr) || total < 0) {
+    set_error("offsets or nbr is NULL, or total < 0");
+    return CHS_E_INVALID;
+  }
+  Alloc al = ix->al;
+  al.stream = st;
+  QueryPlan plan(&al);
+  CHS_TRY(plan_queries(ix, qs, &plan, st));
+  CHS_TRY(radius_fill_impl(ix, plan, r, offsets, nbr, st));
+  return CHS_OK;
+}
+
+extern "C" chs_status chs_radius_search(chs_index ix, const chs_queries* qs, float r,
+                                        const chs_allocator* alloc, int64_t* offsets,
+                                        int32_t** nbr, int64_t* total, hipStream_t st) {
+  clear_error();
+  CHS_TRY(check_queries(ix, qs));
+  CHS_TRY(check_r(r));
+  if (!offsets || !nbr || !total) {
+    set_error("offsets, nbr or total is NULL");
+    return CHS_E_INVALID;
+  }
+  if (alloc && (!alloc->alloc || !alloc->free)) {
+    set_error("allocator callbacks are NULL");
+    return CHS_E_INVALID;
+  }
+  Alloc al = ix->al;
+  al.stream = st;
+  Alloc out_al = al;
+  if (alloc) {
+    out_al.a = *alloc;
+    out_al.has = true;
+  }
+  QueryPlan plan(&al);
+  CHS_TRY(plan_queries(ix, qs, &plan, st));
+  CHS_TRY(radius_count_impl(ix, plan, r, offsets, st));
+  int64_t tot = 0;
+  CHS_HIP(hipMemcpyAsync(&tot, offsets + qs->nq, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  CHS_HIP(hipStreamSynchronize(st));
+  int32_t* out = nullptr;
+  if (tot > 0) {
+    out = static_cast<int32_t*>(out_al.get(sizeof(int32_t) * (size_t)tot));
+    if (!out) {
+      set_error("allocator returned NULL for %lld neighbour indices", (long long)tot);
+      return CHS_E_NOMEM;
+    }
+    chs_status s = radius_fill_impl(ix, plan, r, offsets, out, st);
+    if (s != CHS_OK) {
+      out_al.put(out);
+      return s;
+    }
+  }
+  *nbr = out;
+  *total = tot;
+  return CHS_OK;
+}
+
+extern "C" chs_status chs_knn(chs_index ix, const chs_queries* qs, int32_t k, float r_max,
+                              int32_t* idx, float* d2, hipStream_t st) {
+  clear_error();
+  CHS_TRY(check_queries(ix, qs));
+  if (k < 1 || k > 64) {
+    set_error("k = %d outside [1, 64]", k);
+    return CHS_E_INVALID;
+  }
+  if (std::isnan(r_max) || r_max < 0.0f) {
+    set_error("r_max must be >= 0 or +inf");
+    return CHS_E_INVALID;
+  }
+  if (qs->nq > 0 && (!idx || !d2)) {
+    set_error("idx or d2 is NULL");
+    return CHS_E_INVALID;
+  }
+  if (qs->nq == 0) return CHS_OK;
+  Alloc al = ix->al;
+  al.stream = st;
+  QueryPlan plan(&al);
+  CHS_TRY(plan_queries(ix, qs, &plan, st));
+  const float rmax2 = std::isinf(r_max) ? INFINITY : r_max * r_max;
+  KnnArgs A{plan.q, plan.nq, ix->pts, ix->grid(), ix->voxels(), k, rmax2, idx, d2};
+  const unsigned nb = grid_for(plan.nq);
+  if (k <= 8)
+    k_knn<8><<<nb, kThreads, 0, st>>>(A);
+  else if (k <= 16)
+    k_knn<16><<<nb, kThreads, 0, st>>>(A);
+  else if (k <= 32)
+    k_knn<32><<<nb, kThreads, 0, st>>>(A);
+  else
+    k_knn<64><<<nb, kThreads, 0, st>>>(A);
+  CHS_LAUNCH_CHECK();
+  return CHS_OK;
+}

@@ -1,0 +1,181 @@
+"""Python face of the GPU grid index: marshals torch device tensors into the
+C ABI of libchs.so.  PyTorch provides device memory, streams and (for the
+aggregation) autograd glue; the index, the searches and their results are
+computed by the library's HIP kernels."""
+import ctypes
+import math
+
+import torch
+
+from . import _lib
+from ._lib import BuildParams, IndexArrays, IndexInfo, Queries, check, lib
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class TorchAllocator:
+    """chs_allocator backed by PyTorch's caching allocator on the current
+    stream, so library temporaries and index memory are stream-ordered."""
+
+    def __init__(self, device):
+        self.device = device
+        self._live = {}
+
+        def _alloc(nbytes, ctx):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device,
+                                                       torch.cuda.current_stream(self.device))
+                return p
+            except Exception:  # out of memory -> NULL -> CHS_E_NOMEM
+                return None
+
+        def _free(p, ctx):
+            if p:
+                torch.cuda.caching_allocator_delete(p)
+
+        self._cb_alloc = _lib.ALLOC_FN(_alloc)
+        self._cb_free = _lib.FREE_FN(_free)
+        self.struct = _lib.Allocator(self._cb_alloc, self._cb_free, None)
+
+
+class _DevView:
+    """A borrowed device array exposed through __cuda_array_interface__."""
+
+    def __init__(self, ptr, shape, typestr):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr,
+                                         "data": (int(ptr), False), "version": 2}
+
+
+def _view(ptr, shape, typestr, device):
+    if not ptr or any(s == 0 for s in shape):
+        return None
+    return torch.as_tensor(_DevView(ptr, shape, typestr), device=device)
+
+
+def _queries(queries, n):
+    """Build a chs_queries struct; returns (struct, nq, keepalive)."""
+    if queries is None:
+        return Queries(None, None, n), n, None
+    if not queries.is_cuda:
+        raise ValueError("queries must be a CUDA (HIP) tensor")
+    if queries.dtype == torch.int32 and queries.dim() == 1:
+        q = queries.contiguous()
+        return Queries(None, q.data_ptr() if q.numel() else None, q.numel()), q.numel(), q
+    if queries.dtype == torch.float64 and queries.dim() == 2 and queries.shape[1] == 3:
+        q = queries.contiguous()
+        return Queries(q.data_ptr() if q.numel() else None, None, q.shape[0]), q.shape[0], q
+    raise ValueError("queries: int32 [nq] point indices or float64 [nq,3] coordinates")
+
+
+class GridIndex:
+    """Cheesemap grid index over a cloud ``xyz`` (float64 [n,3] on the GPU).
+
+    flavor: "dense" | "sparse" | "mixed" (Section 3.3); dims: 3 or 2;
+    cell: voxel edge in metres (scalar or per axis)."""
+
+    def __init__(self, xyz, cell=1.0, dims=3, flavor="dense", mixed_dense_pct=80,
+                 max_dense_cells=0, stream=None):
+        if not (isinstance(xyz, torch.Tensor) and xyz.is_cuda and xyz.dtype == torch.float64):
+            raise ValueError("xyz must be a float64 CUDA tensor [n,3]")
+        if xyz.dim() != 2 or xyz.shape[1] != 3:
+            raise ValueError("xyz must have shape [n,3]")
+        self.device = xyz.device
+        self._alloc = TorchAllocator(self.device)
+        xyz = xyz.contiguous()
+        c = [float(cell)] * 3 if not hasattr(cell, "__len__") else [float(v) for v in cell]
+        p = BuildParams(_lib.FLAVORS[flavor], dims, (ctypes.c_double * 3)(*c), mixed_dense_pct, 0,
+                        max_dense_cells)
+        h = ctypes.c_void_p()
+        self._h = None
+        with torch.cuda.device(self.device):
+            st = lib().chs_build(xyz.data_ptr(), xyz.shape[0], ctypes.byref(p),
+                                 ctypes.byref(self._alloc.struct), _stream(stream), ctypes.byref(h))
+        check(st, "chs_build")
+        self._h = h
+        self.n = xyz.shape[0]
+        self.flavor = flavor
+        self.dims = dims
+
+    def close(self):
+        if getattr(self, "_h", None):
+            with torch.cuda.device(self.device):
+                lib().chs_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        inf = IndexInfo()
+        check(lib().chs_index_info(self._h, ctypes.byref(inf)), "chs_index_info")
+        return dict(origin=list(inf.origin), max32=list(inf.max32), cell=list(inf.cell),
+                    ncell=list(inf.ncell), n_points=inf.n_points, n_nonempty=inf.n_nonempty,
+                    n_dense_slices=inf.n_dense_slices, device_bytes=inf.device_bytes,
+                    flavor=inf.flavor, dims=inf.dims)
+
+    def arrays(self):
+        """Copies of the index's device arrays (for inspection and tests)."""
+        a = IndexArrays()
+        check(lib().chs_index_arrays(self._h, ctypes.byref(a)), "chs_index_arrays")
+        inf = self.info()
+        n, m, d = self.n, inf["n_nonempty"], self.device
+        nc = inf["ncell"][0] * inf["ncell"][1] * inf["ncell"][2]
+        out = dict(
+            perm=_view(a.perm, (n,), "<i4", d),
+            inv_perm=_view(a.inv_perm, (n,), "<i4", d),
+            sorted_xyz=_view(a.sorted_xyz, (3, n), "<f4", d),
+            points=_view(a.points, (n, 4), "<f4", d),
+            cell_keys=_view(a.cell_keys, (m,), "<u8", d),
+            cell_start=_view(a.cell_start, (m + 1,), "<i4", d),
+            dense_start=_view(a.dense_start, (nc + 1,), "<i4", d) if a.dense_start else None,
+            slice_dense=_view(a.slice_dense, (inf["ncell"][2],), "|u1", d) if a.slice_dense else None,
+        )
+        torch.cuda.current_stream(d).synchronize()
+        return {k: (None if v is None else v.clone()) for k, v in out.items()}
+
+    # ---- fixed-radius search (Alg. 1)
+    def radius_count(self, r, queries=None, stream=None):
+        q, nq, keep = _queries(queries, self.n)
+        off = torch.empty(nq + 1, dtype=torch.int64, device=self.device)
+        tot = ctypes.c_int64(0)
+        with torch.cuda.device(self.device):
+            check(lib().chs_radius_count(self._h, ctypes.byref(q), ctypes.c_float(r),
+                                         off.data_ptr(), ctypes.byref(tot), _stream(stream)),
+                  "chs_radius_count")
+        return off, tot.value
+
+    def radius_fill(self, r, offsets, total, queries=None, out=None, stream=None):
+        q, nq, keep = _queries(queries, self.n)
+        nbr = out if out is not None else torch.empty(max(total, 0), dtype=torch.int32,
+                                                      device=self.device)
+        with torch.cuda.device(self.device):
+            check(lib().chs_radius_fill(self._h, ctypes.byref(q), ctypes.c_float(r),
+                                        offsets.data_ptr(), nbr.data_ptr() if total else None,
+                                        total, _stream(stream)), "chs_radius_fill")
+        return nbr
+
+    def radius(self, r, queries=None, stream=None):
+        """CSR neighbour lists: (offsets int64 [nq+1], nbr int32 [total]) of
+        original point indices with D <= fl32(r*r)."""
+        off, tot = self.radius_count(r, queries, stream)
+        nbr = self.radius_fill(r, off, tot, queries, stream=stream)
+        return off, nbr
+
+    # ---- k-NN (Section 3.4.2)
+    def knn(self, k, queries=None, r_max=math.inf, stream=None):
+        """(idx int32 [nq,k], d2 float32 [nq,k]) sorted by (d2, index);
+        missing entries are (-1, +inf)."""
+        q, nq, keep = _queries(queries, self.n)
+        idx = torch.empty((nq, k), dtype=torch.int32, device=self.device)
+        d2 = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+        with torch.cuda.device(self.device):
+            check(lib().chs_knn(self._h, ctypes.byref(q), k, ctypes.c_float(r_max),
+                                idx.data_ptr() if nq else None, d2.data_ptr() if nq else None,
+                                _stream(stream)), "chs_knn")
+        return idx, d2

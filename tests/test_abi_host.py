@@ -1,0 +1,100 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/chs.h declares, and rejects invalid arguments on the host before
+touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from tests.conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "chs.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(chs_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2502_11602_amd import lib
+    return lib()
+
+
+def test_header_symbols_exported(L):
+    names = _declared()
+    assert "chs_build" in names and "chs_knn" in names and "chs_radius_search" in names
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in chs.h but not exported"
+
+
+def test_signatures_cover_header():
+    from paper_2502_11602_amd import _lib
+    assert set(_declared()) <= set(_lib.SIGNATURES), "binding misses a declared function"
+
+
+def test_version_and_error_strings(L):
+    assert L.chs_version().startswith(b"chs ")
+    L.chs_free(None)  # NULL is ignored
+
+
+def _params(**kw):
+    from paper_2502_11602_amd._lib import BuildParams
+    d = dict(flavor=0, dims=3, cell=(1.0, 1.0, 1.0), mixed_dense_pct=80, reserved=0,
+             max_dense_cells=0)
+    d.update(kw)
+    return BuildParams(d["flavor"], d["dims"], (ctypes.c_double * 3)(*d["cell"]),
+                       d["mixed_dense_pct"], d["reserved"], d["max_dense_cells"])
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("kw,n,msg", [
+    (dict(), 0, b"n = 0"),
+    (dict(), -5, b"outside"),
+    (dict(dims=4), 10, b"dims"),
+    (dict(dims=1), 10, b"dims"),
+    (dict(flavor=7), 10, b"flavor"),
+    (dict(cell=(0.0, 1.0, 1.0)), 10, b"cell[0]"),
+    (dict(cell=(1.0, float("nan"), 1.0)), 10, b"cell[1]"),
+    (dict(cell=(1.0, 1.0, -2.0)), 10, b"cell[2]"),
+    (dict(mixed_dense_pct=101), 10, b"mixed_dense_pct"),
+    (dict(reserved=1), 10, b"reserved"),
+    (dict(max_dense_cells=-1), 10, b"max_dense_cells"),
+])
+def test_build_rejects_invalid(L, kw, n, msg):
+    h = ctypes.c_void_p()
+    p = _params(**kw)
+    st = L.chs_build(FAKE, n, ctypes.byref(p), None, None, ctypes.byref(h))
+    assert st == 1
+    assert msg in L.chs_last_error()
+    assert not h.value
+
+
+def test_build_rejects_null(L):
+    h = ctypes.c_void_p()
+    p = _params()
+    assert L.chs_build(None, 10, ctypes.byref(p), None, None, ctypes.byref(h)) == 1
+    assert L.chs_build(FAKE, 10, None, None, None, ctypes.byref(h)) == 1
+    assert L.chs_build(FAKE, 10, ctypes.byref(p), None, None, None) == 1
+
+
+def test_queries_reject_null_index(L):
+    from paper_2502_11602_amd._lib import Queries
+    q = Queries(None, None, 0)
+    tot = ctypes.c_int64()
+    assert L.chs_radius_count(None, ctypes.byref(q), 1.0, FAKE, ctypes.byref(tot), None) == 1
+    assert L.chs_knn(None, ctypes.byref(q), 8, float("inf"), FAKE, FAKE, None) == 1
+    assert L.chs_radius_fill(None, ctypes.byref(q), 1.0, FAKE, FAKE, 0, None) == 1
+
+
+def test_2d_cell_z_ignored(L):
+    # with dims == 2 the z edge is not validated (it is not used)
+    h = ctypes.c_void_p()
+    p = _params(dims=2, cell=(1.0, 1.0, 0.0))
+    st = L.chs_build(None, 10, ctypes.byref(p), None, None, ctypes.byref(h))
+    assert st == 1 and b"NULL" in L.chs_last_error()

@@ -1,0 +1,315 @@
+"""GPU parity: the HIP library through its C ABI against the CPU oracle, on
+the same seeded inputs.  Integer results (build arrays, neighbour sets, k-NN
+indices) and the FP32 squared distances must be bit-exact."""
+import math
+
+import numpy as np
+import pytest
+
+import cloudgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _gi():
+    from paper_2502_11602_amd import GridIndex
+    return GridIndex
+
+
+def _walls(seed, n=3000, s=0.5):
+    rng = np.random.default_rng(seed)
+    g = rng.integers(0, 30, size=(n, 3)).astype(np.float64) * s
+    g[: n // 10] = g[n // 10: 2 * (n // 10)]
+    return g + np.array([1000.0, 2000.0, 10.0])
+
+
+def _blob(seed, n=2000):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0, 0.5, (n, 3)) + 7.0
+
+
+def _flat(seed, n=3000):
+    rng = np.random.default_rng(seed)
+    p = rng.uniform(0, 40, (n, 3))
+    p[:, 2] = 3.25
+    return p
+
+
+CLOUDS = {
+    "als": lambda s: cloudgen.small_als(s, 30_000),
+    "walls": _walls,
+    "blob": _blob,
+    "flat": _flat,
+}
+
+
+def _csr_pairs(off, nbr):
+    off = np.asarray(off); nbr = np.asarray(nbr)
+    rows = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    o = np.lexsort((nbr, rows))
+    return rows[o], nbr[o]
+
+
+def _assert_csr_equal(g_off, g_nbr, o_off, o_nbr):
+    g_off = g_off.cpu().numpy() if hasattr(g_off, "cpu") else g_off
+    g_nbr = g_nbr.cpu().numpy() if hasattr(g_nbr, "cpu") else g_nbr
+    np.testing.assert_array_equal(g_off, o_off)
+    gr, gn = _csr_pairs(g_off, g_nbr)
+    orr, on = _csr_pairs(o_off, o_nbr)
+    np.testing.assert_array_equal(gr, orr)
+    np.testing.assert_array_equal(gn, on)
+
+
+# ---------------------------------------------------------------- build
+@pytest.mark.parametrize("name", sorted(CLOUDS))
+@pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
+@pytest.mark.parametrize("dims,s", [(3, 1.0), (3, 0.3), (2, 2.5)])
+def test_build_arrays(name, flavor, dims, s):
+    dev = _dev()
+    xyz = CLOUDS[name](3)
+    gi = _gi()(torch.from_numpy(xyz).to(dev), cell=s, dims=dims, flavor=flavor)
+    ox = oracle.OracleIndex(xyz, s, dims=dims, flavor=flavor)
+    inf = gi.info()
+    assert inf["origin"] == ox.origin.tolist()
+    assert inf["ncell"] == ox.ncell.tolist()
+    np.testing.assert_array_equal(np.array(inf["max32"], np.float32), ox.max32)
+    assert inf["n_nonempty"] == ox.n_nonempty
+    a = gi.arrays()
+    o = ox.point_arrays()
+    np.testing.assert_array_equal(a["perm"].cpu().numpy(), o["perm"])
+    np.testing.assert_array_equal(a["sorted_xyz"].cpu().numpy(), o["sorted"])
+    pts = a["points"].cpu().numpy()
+    np.testing.assert_array_equal(pts[:, :3].T, o["sorted"])
+    np.testing.assert_array_equal(pts[:, 3].view(np.int32), o["perm"])
+    inv = a["inv_perm"].cpu().numpy()
+    np.testing.assert_array_equal(inv[o["perm"]], np.arange(len(xyz)))
+    uk, us = ox.cells()
+    np.testing.assert_array_equal(a["cell_keys"].cpu().numpy(), uk)
+    np.testing.assert_array_equal(a["cell_start"].cpu().numpy(), us)
+    if flavor == "dense":
+        np.testing.assert_array_equal(a["dense_start"].cpu().numpy(), ox.dense_start())
+    else:
+        assert a["dense_start"] is None
+    if flavor == "mixed":
+        ne, de = ox.slices()
+        np.testing.assert_array_equal(a["slice_dense"].cpu().numpy().astype(bool), de)
+        assert inf["n_dense_slices"] == int(de.sum())
+
+
+def test_build_config0_and_determinism():
+    dev = _dev()
+    c = cloudgen.config0()
+    x = torch.from_numpy(c["xyz"]).to(dev)
+    a1 = _gi()(x, cell=1.0).arrays()
+    a2 = _gi()(x, cell=1.0).arrays()
+    for k in a1:
+        if a1[k] is not None:
+            assert torch.equal(a1[k], a2[k]), k
+    ox = oracle.OracleIndex(c["xyz"], 1.0)
+    np.testing.assert_array_equal(a1["perm"].cpu().numpy(), ox.point_arrays()["perm"])
+
+
+# ---------------------------------------------------------------- radius
+@pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
+@pytest.mark.parametrize("r", [0.0, 0.5, 1.0, 2.5])
+def test_radius_config0(flavor, r):
+    dev = _dev()
+    c = cloudgen.config0()
+    gi = _gi()(torch.from_numpy(c["xyz"]).to(dev), cell=c["cell"], flavor=flavor)
+    ox = oracle.OracleIndex(c["xyz"], c["cell"], flavor=flavor)
+    q = c["queries"]
+    off, nbr = gi.radius(r, torch.from_numpy(q).to(dev))
+    ooff, onbr = ox.radius(r, pidx=q, nthreads=8)
+    _assert_csr_equal(off, nbr, ooff, onbr)
+
+
+@pytest.mark.parametrize("name", sorted(CLOUDS))
+@pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
+@pytest.mark.parametrize("dims,s", [(3, 1.0), (3, 0.3), (2, 2.5)])
+def test_radius_all_points(name, flavor, dims, s):
+    dev = _dev()
+    xyz = CLOUDS[name](4)
+    gi = _gi()(torch.from_numpy(xyz).to(dev), cell=s, dims=dims, flavor=flavor)
+    ox = oracle.OracleIndex(xyz, s, dims=dims, flavor=flavor)
+    r = 0.7 if name != "blob" else 0.05
+    off, nbr = gi.radius(r)
+    ooff, onbr = ox.radius(r, nthreads=8)
+    _assert_csr_equal(off, nbr, ooff, onbr)
+
+
+@pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
+def test_radius_coordinate_queries(flavor):
+    dev = _dev()
+    xyz = cloudgen.small_als(8, 40_000)
+    rng = np.random.default_rng(11)
+    qa = rng.uniform(xyz.min(0) - 4.0, xyz.max(0) + 4.0, (5000, 3))
+    qa[:50] = xyz[:50]  # exactly on cloud points
+    gi = _gi()(torch.from_numpy(xyz).to(dev), cell=1.0, flavor=flavor)
+    ox = oracle.OracleIndex(xyz, 1.0, flavor=flavor)
+    for r in (0.6, 3.0):
+        off, nbr = gi.radius(r, torch.from_numpy(qa).to(dev))
+        ooff, onbr = ox.radius(r, qxyz=qa, nthreads=8)
+        _assert_csr_equal(off, nbr, ooff, onbr)
+
+
+def test_radius_edge_cases():
+    dev = _dev()
+    GI = _gi()
+    # single point
+    one = GI(torch.tensor([[5.0, 6.0, 7.0]], dtype=torch.float64, device=dev), cell=1.0)
+    off, nbr = one.radius(0.0)
+    assert off.tolist() == [0, 1] and nbr.tolist() == [0]
+    # no queries
+    xyz = _walls(1)
+    gi = GI(torch.from_numpy(xyz).to(dev), cell=0.5)
+    off, nbr = gi.radius(1.0, torch.empty(0, dtype=torch.int32, device=dev))
+    assert off.tolist() == [0] and nbr.numel() == 0
+    # out-of-range point indices give empty rows
+    q = torch.tensor([0, -1, len(xyz), 5], dtype=torch.int32, device=dev)
+    off, nbr = gi.radius(1.0, q)
+    c = torch.diff(off).cpu().numpy()
+    assert c[1] == 0 and c[2] == 0 and c[0] > 0 and c[3] > 0
+    # radius beyond the bounding-box diagonal: every point
+    off, nbr = gi.radius(1000.0, torch.arange(0, len(xyz), 97, dtype=torch.int32, device=dev))
+    assert (torch.diff(off) == len(xyz)).all()
+    # deterministic fill order
+    o1, n1 = gi.radius(2.0)
+    o2, n2 = gi.radius(2.0)
+    assert torch.equal(o1, o2) and torch.equal(n1, n2)
+
+
+def test_radius_rejects_bad_radius():
+    from paper_2502_11602_amd import ChsError
+    dev = _dev()
+    gi = _gi()(torch.from_numpy(_walls(2)).to(dev), cell=0.5)
+    for r in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(ChsError):
+            gi.radius(r)
+
+
+# ---------------------------------------------------------------- k-NN
+@pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
+@pytest.mark.parametrize("k", [1, 5, 16, 33, 64])
+def test_knn_config0(flavor, k):
+    dev = _dev()
+    c = cloudgen.config0()
+    gi = _gi()(torch.from_numpy(c["xyz"]).to(dev), cell=c["cell"], flavor=flavor)
+    ox = oracle.OracleIndex(c["xyz"], c["cell"], flavor=flavor)
+    q = c["queries"]
+    idx, d2 = gi.knn(k, torch.from_numpy(q).to(dev))
+    oi, od = ox.knn(k, pidx=q, nthreads=8)
+    np.testing.assert_array_equal(idx.cpu().numpy(), oi)
+    np.testing.assert_array_equal(d2.cpu().numpy(), od)
+
+
+@pytest.mark.parametrize("name", sorted(CLOUDS))
+@pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
+@pytest.mark.parametrize("dims,s", [(3, 1.0), (3, 0.3), (2, 2.5)])
+def test_knn_all_points(name, flavor, dims, s):
+    dev = _dev()
+    xyz = CLOUDS[name](6)
+    gi = _gi()(torch.from_numpy(xyz).to(dev), cell=s, dims=dims, flavor=flavor)
+    ox = oracle.OracleIndex(xyz, s, dims=dims, flavor=flavor)
+    for k in (8, 20):
+        idx, d2 = gi.knn(k)
+        oi, od = ox.knn(k, nthreads=8)
+        np.testing.assert_array_equal(idx.cpu().numpy(), oi)
+        np.testing.assert_array_equal(d2.cpu().numpy(), od)
+
+
+@pytest.mark.parametrize("flavor", ["dense", "sparse"])
+def test_knn_coordinate_queries_and_rmax(flavor):
+    dev = _dev()
+    xyz = cloudgen.small_als(9, 30_000)
+    rng = np.random.default_rng(12)
+    qa = rng.uniform(xyz.min(0) - 6.0, xyz.max(0) + 6.0, (4000, 3))
+    gi = _gi()(torch.from_numpy(xyz).to(dev), cell=1.0, flavor=flavor)
+    ox = oracle.OracleIndex(xyz, 1.0, flavor=flavor)
+    for rmax in (math.inf, 0.8, 3.0):
+        idx, d2 = gi.knn(12, torch.from_numpy(qa).to(dev), r_max=rmax)
+        oi, od = ox.knn(12, r_max=rmax, qxyz=qa, nthreads=8)
+        np.testing.assert_array_equal(idx.cpu().numpy(), oi)
+        np.testing.assert_array_equal(d2.cpu().numpy(), od)
+
+
+def test_knn_edge_cases():
+    dev = _dev()
+    GI = _gi()
+    # fewer points than k
+    xyz = np.random.default_rng(0).uniform(0, 3, (10, 3))
+    gi = GI(torch.from_numpy(xyz).to(dev), cell=1.0)
+    idx, d2 = gi.knn(16)
+    oi, od = oracle.OracleIndex(xyz, 1.0).knn(16)
+    np.testing.assert_array_equal(idx.cpu().numpy(), oi)
+    np.testing.assert_array_equal(d2.cpu().numpy(), od)
+    assert (idx[:, 10:] == -1).all()
+    # duplicates: ties broken by original index
+    w = _walls(5)
+    gi = GI(torch.from_numpy(w).to(dev), cell=0.5)
+    idx, d2 = gi.knn(24)
+    oi, od = oracle.OracleIndex(w, 0.5).knn(24)
+    np.testing.assert_array_equal(idx.cpu().numpy(), oi)
+    np.testing.assert_array_equal(d2.cpu().numpy(), od)
+    # invalid point indices give (-1, inf) rows
+    q = torch.tensor([3, -7, len(w)], dtype=torch.int32, device=dev)
+    idx, d2 = gi.knn(4, q)
+    assert (idx[1:] == -1).all() and torch.isinf(d2[1:]).all() and (idx[0] >= 0).all()
+    # k-prefix property and determinism
+    i8, _ = gi.knn(8)
+    i32, _ = gi.knn(32)
+    assert torch.equal(i32[:, :8], i8)
+    assert torch.equal(gi.knn(32)[0], i32)
+
+
+# ---------------------------------------------------------------- full size
+@pytest.mark.slow
+def test_config1_full_size_sampled():
+    """The 10 M-point ALS tile, every point a query, in the launch
+    configuration the benchmark times; a seeded sample of rows is checked
+    against the oracle exactly, and the whole radius relation for symmetry."""
+    dev = _dev()
+    c = cloudgen.config1()
+    xyz = c["xyz"]
+    n = len(xyz)
+    gi = _gi()(torch.from_numpy(xyz).to(dev), cell=1.0)
+    ox = oracle.OracleIndex(xyz, 1.0)
+    samp = np.sort(np.random.default_rng(42).choice(n, 3000, replace=False)).astype(np.int32)
+    st = torch.from_numpy(samp.astype(np.int64)).to(dev)
+    for r in c["radii"]:
+        off, nbr = gi.radius(r)
+        counts = torch.diff(off)
+        ooff, onbr = ox.radius(r, pidx=samp, nthreads=8)
+        np.testing.assert_array_equal(counts[st].cpu().numpy(), np.diff(ooff))
+        rows = []
+        offc = off.cpu().numpy()
+        nb = nbr.cpu().numpy() if r <= 1.0 else None
+        for t, p in enumerate(samp):
+            g = nb[offc[p]:offc[p + 1]] if nb is not None else \
+                nbr[int(offc[p]):int(offc[p + 1])].cpu().numpy()
+            rows.append(np.sort(g))
+        got = np.concatenate(rows)
+        want = np.concatenate([np.sort(onbr[ooff[t]:ooff[t + 1]]) for t in range(len(samp))])
+        np.testing.assert_array_equal(got, want)
+        if r == 1.0:
+            # symmetry of the whole relation: the multiset of pairs is closed
+            # under swapping (compared through two order-independent sums)
+            rowi = torch.repeat_interleave(torch.arange(n, device=dev), counts)
+            a = rowi.to(torch.int64) * 1_000_003 + nbr.to(torch.int64)
+            b = nbr.to(torch.int64) * 1_000_003 + rowi.to(torch.int64)
+            h = lambda v: ((v * 0x9E3779B97F4A7C15) >> 17) & 0xFFFFFFFF  # noqa: E731
+            assert int(h(a).sum()) == int(h(b).sum())
+        del off, nbr
+    for k in c["ks"]:
+        idx, d2 = gi.knn(k)
+        oi, od = ox.knn(k, pidx=samp, nthreads=8)
+        np.testing.assert_array_equal(idx[st].cpu().numpy(), oi)
+        np.testing.assert_array_equal(d2[st].cpu().numpy(), od)
