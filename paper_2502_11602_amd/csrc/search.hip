@@ -268,7 +268,9 @@ __global__ __launch_bounds__(kThreads) void k_radius(RadiusArgs A) {
   const bool active = in && !(wq & kInactive);
   const uint32_t qid = wq & ~kInactive;
   const Tile tb = tile_bounds(q, active);
-  const float R = A.r * A.r;  // fl32(r*r)
+  // fl32(r*r); lanes without a valid query get a negative bound so that no
+  // candidate (D >= 0, or NaN) ever matches for them and they write nothing
+  const float R = active ? A.r * A.r : -1.0f;
   const double pad = fmax((double)A.r * (1.0 + kPadRel), kPadAbs);
   int32_t cnt = 0;
   int64_t obase = 0;
