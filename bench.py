@@ -102,6 +102,9 @@ def main():
     ap.add_argument("--points", type=int, default=10_000_000)
     ap.add_argument("--cpu-sample", type=int, default=20_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device-to-device copy of this size before the steps "
+                         "(a known-size kernel for scaling hardware byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -126,6 +129,16 @@ def main():
     dev = torch.device("cuda:0")
     x = torch.from_numpy(xyz).to(dev)
     torch.cuda.synchronize()
+
+    if args.copy_calibration_mib > 0:
+        nel = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {nel * 4} bytes read, {nel * 4} bytes written",
+              file=sys.stderr, flush=True)
+        del src, dst
 
     E = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
 

@@ -62,17 +62,37 @@ __global__ __launch_bounds__(kThreads) void k_bbox(const double* __restrict__ xy
   }
 }
 
-__global__ void k_bbox_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
-  if (threadIdx.x != 0) return;
+// One block of 256 threads folds the per-block partials.
+__global__ __launch_bounds__(kThreads) void k_bbox_final(const double* __restrict__ part, int nb,
+                                                         double* __restrict__ out) {
   double r[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0};
-  for (int b = 0; b < nb; ++b) {
+  for (int b = threadIdx.x; b < nb; b += kThreads) {
     for (int a = 0; a < 3; ++a) {
       r[a] = part[b * 7 + a] < r[a] ? part[b * 7 + a] : r[a];
       r[3 + a] = part[b * 7 + 3 + a] > r[3 + a] ? part[b * 7 + 3 + a] : r[3 + a];
     }
     r[6] = part[b * 7 + 6] > r[6] ? part[b * 7 + 6] : r[6];
   }
-  for (int a = 0; a < 7; ++a) out[a] = r[a];
+  __shared__ double s[kThreads / kWave][7];
+  const int w = threadIdx.x / kWave;
+  for (int a = 0; a < 3; ++a) {
+    r[a] = wave_min(r[a]);
+    r[3 + a] = wave_max(r[3 + a]);
+  }
+  r[6] = wave_max(r[6]);
+  if (lane_id() == 0)
+    for (int a = 0; a < 7; ++a) s[w][a] = r[a];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < kThreads / kWave; ++q) {
+      for (int a = 0; a < 3; ++a) {
+        r[a] = s[q][a] < r[a] ? s[q][a] : r[a];
+        r[3 + a] = s[q][3 + a] > r[3 + a] ? s[q][3 + a] : r[3 + a];
+      }
+      r[6] = s[q][6] > r[6] ? s[q][6] : r[6];
+    }
+    for (int a = 0; a < 7; ++a) out[a] = r[a];
+  }
 }
 
 // ---------------------------------------------------------------- keys
@@ -417,7 +437,7 @@ static chs_status build_impl(chs_index ix, const double* xyz, int64_t n) {
   if (nb > kBoxBlocks) nb = kBoxBlocks;
   k_bbox<<<nb, kThreads, 0, st>>>(xyz, n, part.as<double>());
   CHS_LAUNCH_CHECK();
-  k_bbox_final<<<1, 64, 0, st>>>(part.as<double>(), nb, bb.as<double>());
+  k_bbox_final<<<1, kThreads, 0, st>>>(part.as<double>(), nb, bb.as<double>());
   CHS_LAUNCH_CHECK();
   double h[7];
   CHS_HIP(hipMemcpyAsync(h, bb.p, sizeof(h), hipMemcpyDeviceToHost, st));

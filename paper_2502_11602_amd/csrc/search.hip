@@ -255,8 +255,42 @@ struct RadiusArgs {
   int32_t* __restrict__ nbr;            // fill pass
 };
 
+// Fill-pass staging: each lane appends its matches to a private LDS
+// segment; when any segment is full the wave flushes them all, writing each
+// lane's segment to that lane's CSR row as one contiguous run (two rows per
+// store instruction, one per half-wave) instead of 64 scattered 4-byte
+// stores per candidate, which the memory system would write back as 64
+// partial lines.  Every store is also checked against its row's end.
+constexpr int kStage = 32;                 // entries per lane
+constexpr int kStageStride = kStage + 1;   // padded against LDS bank conflicts
+
+__device__ __forceinline__ void flush_stage(const int32_t* seg_base, int lane, int& nb,
+                                            int64_t& wpos, int64_t wend,
+                                            int32_t* __restrict__ nbr) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const int half = lane >> 5, i = lane & 31;
+  const uint64_t pending = __ballot(nb > 0);
+  // pairs of lanes (2m, 2m+1) with anything staged
+  uint64_t pairs = (pending | (pending >> 1)) & 0x5555555555555555ull;
+  while (pairs) {
+    const int m2 = __builtin_ctzll(pairs);
+    pairs &= pairs - 1;
+    const int src = m2 + half;
+    const int cnt = __shfl(nb, src, kWave);
+    const int64_t base = __shfl(wpos, src, kWave);
+    const int64_t end = __shfl(wend, src, kWave);
+    if (i < cnt && base + i < end) nbr[base + i] = seg_base[src * kStageStride + i];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  wpos += nb;
+  nb = 0;
+}
+
 template <bool FILL>
 __global__ __launch_bounds__(kThreads) void k_radius(RadiusArgs A) {
+  __shared__ int32_t s_stage[FILL ? kWavesPerBlock * kWave * kStageStride : 1];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t t0 = ((int64_t)blk * kWavesPerBlock + w) * kWave;
@@ -265,7 +299,7 @@ __global__ __launch_bounds__(kThreads) void k_radius(RadiusArgs A) {
   const bool in = t < A.nq;
   const float4 q = in ? A.q4[t] : make_float4(0.f, 0.f, 0.f, __uint_as_float(kInactive));
   const uint32_t wq = __float_as_uint(q.w);
-  const bool active = in && !(wq & kInactive);
+  const bool active = in && !(wq & kInactive) && (int64_t)(wq & ~kInactive) < A.nq;
   const uint32_t qid = wq & ~kInactive;
   const Tile tb = tile_bounds(q, active);
   // fl32(r*r); lanes without a valid query get a negative bound so that no
@@ -273,8 +307,14 @@ __global__ __launch_bounds__(kThreads) void k_radius(RadiusArgs A) {
   const float R = active ? A.r * A.r : -1.0f;
   const double pad = fmax((double)A.r * (1.0 + kPadRel), kPadAbs);
   int32_t cnt = 0;
-  int64_t obase = 0;
-  if (FILL && active) obase = A.offsets[qid];
+  int64_t wpos = 0, wend = 0;
+  int nb = 0;
+  int32_t* seg_base = s_stage + (FILL ? w * kWave * kStageStride : 0);
+  int32_t* my_seg = seg_base + (FILL ? lane * kStageStride : 0);
+  if (FILL && active) {
+    wpos = A.offsets[qid];
+    wend = A.offsets[qid + 1];
+  }
   if (tb.any) {
     const VBox bx = voxel_box(A.g, tb.lo, tb.hi, pad);
     if (!bx.empty) {
@@ -293,21 +333,29 @@ __global__ __launch_bounds__(kThreads) void k_radius(RadiusArgs A) {
           m &= m - 1;
           const int32_t rb = __builtin_amdgcn_readlane(b, src);
           const int32_t re = __builtin_amdgcn_readlane(e, src);
+          if (!FILL) {
 #pragma unroll 4
-          for (int32_t p = rb; p < re; ++p) {
-            const float4 P = A.pts[p];
-            const float dx = q.x - P.x, dy = q.y - P.y, dz = q.z - P.z;
-            const float D = (dx * dx + dy * dy) + dz * dz;
-            if (D <= R) {
-              if (FILL) A.nbr[obase + cnt] = __float_as_int(P.w);
-              ++cnt;
+            for (int32_t p = rb; p < re; ++p) {
+              const float4 P = A.pts[p];
+              const float dx = q.x - P.x, dy = q.y - P.y, dz = q.z - P.z;
+              const float D = (dx * dx + dy * dy) + dz * dz;
+              cnt += D <= R ? 1 : 0;
+            }
+          } else {
+            for (int32_t p = rb; p < re; ++p) {
+              const float4 P = A.pts[p];
+              const float dx = q.x - P.x, dy = q.y - P.y, dz = q.z - P.z;
+              const float D = (dx * dx + dy * dy) + dz * dz;
+              if (D <= R) my_seg[nb++] = __float_as_int(P.w);
+              if (__ballot(nb == kStage)) flush_stage(seg_base, lane, nb, wpos, wend, A.nbr);
             }
           }
         }
       }
     }
   }
-  if (!FILL && in) A.counts[qid] = active ? cnt : 0;
+  if (FILL) flush_stage(seg_base, lane, nb, wpos, wend, A.nbr);
+  if (!FILL && in && qid < A.nq) A.counts[qid] = active ? cnt : 0;
 }
 
 // ---------------------------------------------------------------- k-NN
