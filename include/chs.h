@@ -176,6 +176,35 @@ chs_status chs_radius_search(chs_index index, const chs_queries* queries, float 
 chs_status chs_knn(chs_index index, const chs_queries* queries, int32_t k, float r_max,
                    int32_t* idx, float* d2, hipStream_t stream);
 
+/* ---- Gaussian-weighted neighbourhood aggregation (a project addition) ----
+ * out[q,c] = sum_t w_qt f[j_t, c] with w_qt = exp(-D(x_j, x_q) / (2 sigma^2)),
+ * x_q = x[qidx[q]], j_t = nbr[q,t]; negative or out-of-range entries of nbr
+ * are padding and contribute nothing.  D is the unfused squared distance in
+ * the compute type.  Typical neighbour lists come from chs_knn (the k nearest
+ * within r_max) over the same points.
+ *   x     [N,3]  coordinates (recentred), x_dtype
+ *   f     [N,C]  features, f_dtype;   out, grad_out, grad_f [Q,C] f_dtype
+ *   qidx  [Q]    centre point of each query; nbr [Q,K] int32
+ * dtype pairs: (CHS_F32, CHS_F32), (CHS_F32, CHS_BF16) computing in FP32, and
+ * (CHS_F64, CHS_F64) computing in FP64; others give CHS_E_UNSUPPORTED.  Sums
+ * run in a fixed order, so results are bitwise reproducible. */
+typedef enum chs_dtype { CHS_F32 = 0, CHS_F64 = 1, CHS_BF16 = 2 } chs_dtype;
+
+chs_status chs_gauss_agg_fwd(const void* x, const int32_t* qidx, const int32_t* nbr, int64_t N,
+                             int64_t Q, int32_t K, const void* f, int32_t C, double sigma,
+                             int32_t x_dtype, int32_t f_dtype, void* out, hipStream_t stream);
+
+/* Gradient of sum_{q,c} grad_out[q,c] out[q,c] with the neighbour lists held
+ * fixed: grad_x [N,3] (x_dtype; both the neighbour and the centre role of
+ * every point) and grad_f [N,C] (f_dtype), both fully overwritten.  Pairs
+ * are regrouped by neighbour with a stable sort and summed segment by
+ * segment (no floating-point atomics).  Temporaries (about 24 bytes per pair)
+ * come from `alloc` (NULL: stream-ordered hipMallocAsync). */
+chs_status chs_gauss_agg_bwd(const void* x, const int32_t* qidx, const int32_t* nbr, int64_t N,
+                             int64_t Q, int32_t K, const void* f, int32_t C, double sigma,
+                             int32_t x_dtype, int32_t f_dtype, const void* grad_out, void* grad_x,
+                             void* grad_f, const chs_allocator* alloc, hipStream_t stream);
+
 /* Release the index and its device memory (stream-ordered on the stream it
  * was built with).  NULL is ignored. */
 void chs_free(chs_index index);

@@ -58,6 +58,12 @@ SIGNATURES = {
                                     ctypes.POINTER(c_int64), c_void_p]),
     "chs_knn": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_int32, c_float, c_void_p, c_void_p,
                           c_void_p]),
+    "chs_gauss_agg_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_int32,
+                                    c_void_p, c_int32, c_double, c_int32, c_int32, c_void_p,
+                                    c_void_p]),
+    "chs_gauss_agg_bwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_int32,
+                                    c_void_p, c_int32, c_double, c_int32, c_int32, c_void_p,
+                                    c_void_p, c_void_p, ctypes.POINTER(Allocator), c_void_p]),
     "chs_free": (None, [c_void_p]),
     "chs_last_error": (ctypes.c_char_p, []),
     "chs_version": (ctypes.c_char_p, []),

@@ -1,0 +1,122 @@
+"""GPU parity of the differentiable Gaussian aggregation against the FP64
+CPU reference (whose gradient is itself pinned by finite differences), plus
+torch.autograd.gradcheck in FP64.  Tolerances: FP32 max|d| / max|ref| <= 1e-4
+per output tensor; BF16 <= 1e-2 against the reference computed from the
+BF16-rounded inputs; FP64 <= 1e-10."""
+import numpy as np
+import pytest
+
+import cloudgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _case(n, nq, channels, seed=4, k=64, r_max=0.5):
+    from paper_2502_11602_amd import GridIndex, neighbour_lists
+    from paper_2502_11602_amd.agg import recentred
+    dev = _dev()
+    c = cloudgen.config4(seed=seed, n=n, nq=nq, channels=channels)
+    x64 = torch.from_numpy(c["xyz"]).to(dev)
+    ix = GridIndex(x64, cell=0.5)
+    q = torch.from_numpy(c["queries"]).to(dev)
+    nbr = neighbour_lists(ix, q, k=k, r_max=r_max)
+    x32 = recentred(x64, ix)
+    return c, x32, q, nbr
+
+
+def _reference(x, q, nbr, f, g, sigma):
+    xr = x.detach().double().cpu().numpy()
+    fr = f.detach().double().cpu().numpy()
+    qn = q.cpu().numpy(); nn = nbr.cpu().numpy()
+    out = oracle.agg_forward(xr, qn, nn, fr, sigma)
+    gx, gf = oracle.agg_backward(xr, qn, nn, fr, sigma, g.detach().double().cpu().numpy())
+    return out, gx, gf
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-4), (torch.bfloat16, 1e-2)])
+def test_agg_matches_reference(dtype, tol):
+    from paper_2502_11602_amd import gauss_aggregate
+    c, x32, q, nbr = _case(40_000, 8_000, 64)
+    dev = x32.device
+    f = torch.from_numpy(c["f"]).to(dev).to(dtype).requires_grad_(True)
+    x = x32.clone().requires_grad_(True)
+    out = gauss_aggregate(x, f, q, nbr, sigma=c["sigma"])
+    g = torch.randn(out.shape, generator=torch.Generator().manual_seed(1)).to(dev).to(dtype)
+    out.backward(g)
+    ro, rgx, rgf = _reference(x, q, nbr, f, g, c["sigma"])
+    assert (nbr >= 0).sum(1).float().mean() > 10  # neighbourhoods are populated
+    assert _rel(out.detach().double().cpu().numpy(), ro) <= tol
+    assert _rel(x.grad.double().cpu().numpy(), rgx) <= tol
+    assert _rel(f.grad.double().cpu().numpy(), rgf) <= tol
+
+
+def test_agg_fp64_exact_and_gradcheck():
+    from paper_2502_11602_amd import GaussAgg
+    c, x32, q, nbr = _case(2_000, 500, 8, seed=44)
+    dev = x32.device
+    x = x32.double().clone().requires_grad_(True)
+    f = torch.from_numpy(c["f"]).to(dev).double().requires_grad_(True)
+    sigma = c["sigma"]
+    out = GaussAgg.apply(x, f, q, nbr, sigma)
+    g = torch.randn(out.shape, dtype=torch.float64, generator=torch.Generator().manual_seed(2)).to(dev)
+    out.backward(g)
+    ro, rgx, rgf = _reference(x, q, nbr, f, g, sigma)
+    assert _rel(out.detach().cpu().numpy(), ro) <= 1e-10
+    assert _rel(x.grad.cpu().numpy(), rgx) <= 1e-10
+    assert _rel(f.grad.cpu().numpy(), rgf) <= 1e-10
+    fn = lambda xx, ff: GaussAgg.apply(xx, ff, q, nbr, sigma)  # noqa: E731
+    assert torch.autograd.gradcheck(fn, (x.detach().requires_grad_(True),
+                                         f.detach().requires_grad_(True)),
+                                    eps=1e-6, atol=1e-7, rtol=1e-5, fast_mode=True)
+
+
+def test_agg_deterministic_and_special_cases():
+    from paper_2502_11602_amd import gauss_aggregate
+    c, x32, q, nbr = _case(20_000, 4_000, 64, seed=7)
+    dev = x32.device
+    f = torch.from_numpy(c["f"]).to(dev)
+    grads = []
+    for _ in range(2):
+        x = x32.clone().requires_grad_(True)
+        ff = f.clone().requires_grad_(True)
+        out = gauss_aggregate(x, ff, q, nbr, sigma=0.25)
+        out.backward(torch.ones_like(out))
+        grads.append((out.detach(), x.grad, ff.grad))
+    for a, b in zip(grads[0], grads[1]):
+        assert torch.equal(a, b)
+    # a list holding only the centre returns its feature exactly
+    only = torch.full_like(nbr, -1)
+    only[:, 0] = q
+    out = gauss_aggregate(x32, f, q, only, sigma=0.25)
+    assert torch.equal(out, f[q.long()])
+
+
+@pytest.mark.slow
+def test_agg_config4_full_size():
+    """1 M points at 50 points per square metre, 64 channels, 250 k centres,
+    64 nearest within 0.5 m, sigma 0.25 m (FP32)."""
+    from paper_2502_11602_amd import gauss_aggregate
+    c, x32, q, nbr = _case(1_000_000, 250_000, 64)
+    dev = x32.device
+    f = torch.from_numpy(c["f"]).to(dev).requires_grad_(True)
+    x = x32.clone().requires_grad_(True)
+    out = gauss_aggregate(x, f, q, nbr, sigma=c["sigma"])
+    g = torch.randn(out.shape, generator=torch.Generator().manual_seed(3)).to(dev)
+    out.backward(g)
+    ro, rgx, rgf = _reference(x, q, nbr, f, g, c["sigma"])
+    assert _rel(out.detach().double().cpu().numpy(), ro) <= 1e-4
+    assert _rel(x.grad.double().cpu().numpy(), rgx) <= 1e-4
+    assert _rel(f.grad.double().cpu().numpy(), rgf) <= 1e-4
