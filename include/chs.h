@@ -116,10 +116,37 @@ typedef struct chs_index_info_t {
   int64_t n_dense_slices; /* MIXED: slices stored densely                 */
   int64_t device_bytes; /* memory held by the index                      */
   int32_t flavor, dims;
+  int32_t ntiles;       /* 1, or the number of tiles of a batched index  */
+  int32_t reserved;
 } chs_index_info_t;
 
-/* Host-side description of a built index.  No device work. */
+/* Host-side description of a built index (for a batched index: tile 0's
+ * geometry and the totals).  No device work. */
 chs_status chs_index_info(chs_index index, chs_index_info_t* out /* host */);
+
+/* Batched build: ntiles independent clouds stored back to back in xyz
+ * [n,3]; tile t holds input points [tile_off[t], tile_off[t+1]) (tile_off
+ * is a host array of ntiles+1 entries, from 0 to n, strictly increasing).
+ * Each tile gets its own bounding box, grid and voxel edges (params[t],
+ * host array of ntiles entries, one flavor for all; MIXED is single-tile
+ * only).  The tiles' voxel key spaces are concatenated, so keying, sorting
+ * and the voxel maps run once for the whole batch.  Searches on a batched
+ * index take "every point" queries only (each point queries its own tile);
+ * their rows follow the input order and neighbour indices are tile-local
+ * (input index minus tile_off[t]). */
+chs_status chs_build_batch(const double* xyz, int64_t n, const int64_t* tile_off /* host */,
+                           int32_t ntiles, const chs_build_params* params /* host */,
+                           const chs_allocator* alloc, hipStream_t stream, chs_index* out);
+
+/* Geometry of one tile of a batched index (n_nonempty is -1). */
+chs_status chs_tile_info(chs_index index, int32_t tile, chs_index_info_t* out /* host */);
+
+/* CHS_OPT_PERSISTENT (default: on for batched indexes, off otherwise):
+ * searches launch one wave per hardware slot and the waves pull 64-query
+ * work items (largest tiles first) from a device counter until none is left,
+ * instead of one wave per work item.  Results are identical either way. */
+typedef enum chs_option { CHS_OPT_PERSISTENT = 1 } chs_option;
+chs_status chs_index_set_option(chs_index index, int32_t option, int64_t value);
 
 /* Device arrays of a built index, borrowed (valid until chs_free, never to
  * be written).  perm[pos] = original index of the pos-th stored point;

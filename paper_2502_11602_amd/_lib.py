@@ -34,7 +34,7 @@ class IndexInfo(ctypes.Structure):
     _fields_ = [("origin", c_double * 3), ("max32", c_float * 3), ("cell", c_double * 3),
                 ("ncell", c_int64 * 3), ("n_points", c_int64), ("n_nonempty", c_int64),
                 ("n_dense_slices", c_int64), ("device_bytes", c_int64), ("flavor", c_int32),
-                ("dims", c_int32)]
+                ("dims", c_int32), ("ntiles", c_int32), ("reserved", c_int32)]
 
 
 class IndexArrays(ctypes.Structure):
@@ -48,6 +48,10 @@ SIGNATURES = {
     "chs_build": (c_int32, [c_void_p, c_int64, ctypes.POINTER(BuildParams),
                             ctypes.POINTER(Allocator), c_void_p, ctypes.POINTER(c_void_p)]),
     "chs_index_info": (c_int32, [c_void_p, ctypes.POINTER(IndexInfo)]),
+    "chs_build_batch": (c_int32, [c_void_p, c_int64, c_void_p, c_int32, c_void_p,
+                                  ctypes.POINTER(Allocator), c_void_p, ctypes.POINTER(c_void_p)]),
+    "chs_tile_info": (c_int32, [c_void_p, c_int32, ctypes.POINTER(IndexInfo)]),
+    "chs_index_set_option": (c_int32, [c_void_p, c_int32, c_int64]),
     "chs_index_arrays": (c_int32, [c_void_p, ctypes.POINTER(IndexArrays)]),
     "chs_radius_count": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_float, c_void_p,
                                    ctypes.POINTER(c_int64), c_void_p]),

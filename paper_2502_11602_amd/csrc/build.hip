@@ -23,56 +23,16 @@ static unsigned grid_for(int64_t n, int per_block = kThreads) {
 }
 
 // ---------------------------------------------------------------- bbox
-constexpr int kBoxBlocks = 1024;
+// Per-tile FP64 bounding boxes (Eq. 1-2): blocks reduce chunks of one tile
+// each, then one block per tile folds its chunks.  Also flags non-finite
+// coordinates.
+constexpr int64_t kBoxChunk = 1 << 16;
 
-__global__ __launch_bounds__(kThreads) void k_bbox(const double* __restrict__ xyz, int64_t n,
-                                                   double* __restrict__ part) {
-  double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-  double bad = 0.0;
-  for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < n;
-       p += (int64_t)gridDim.x * kThreads) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double v = xyz[p * 3 + a];
-      if (!isfinite(v)) bad = 1.0;
-      mn[a] = v < mn[a] ? v : mn[a];
-      mx[a] = v > mx[a] ? v : mx[a];
-    }
-  }
-  __shared__ double s[kThreads / kWave][7];
-  const int w = threadIdx.x / kWave;
-  double r[7];
-  for (int a = 0; a < 3; ++a) {
-    r[a] = wave_min(mn[a]);
-    r[3 + a] = wave_max(mx[a]);
-  }
-  r[6] = wave_max(bad);
-  if (lane_id() == 0)
-    for (int a = 0; a < 7; ++a) s[w][a] = r[a];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int q = 1; q < kThreads / kWave; ++q) {
-      for (int a = 0; a < 3; ++a) {
-        r[a] = s[q][a] < r[a] ? s[q][a] : r[a];
-        r[3 + a] = s[q][3 + a] > r[3 + a] ? s[q][3 + a] : r[3 + a];
-      }
-      r[6] = s[q][6] > r[6] ? s[q][6] : r[6];
-    }
-    for (int a = 0; a < 7; ++a) part[blockIdx.x * 7 + a] = r[a];
-  }
-}
+struct Chunk {
+  int64_t begin, end;
+};
 
-// One block of 256 threads folds the per-block partials.
-__global__ __launch_bounds__(kThreads) void k_bbox_final(const double* __restrict__ part, int nb,
-                                                         double* __restrict__ out) {
-  double r[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0};
-  for (int b = threadIdx.x; b < nb; b += kThreads) {
-    for (int a = 0; a < 3; ++a) {
-      r[a] = part[b * 7 + a] < r[a] ? part[b * 7 + a] : r[a];
-      r[3 + a] = part[b * 7 + 3 + a] > r[3 + a] ? part[b * 7 + 3 + a] : r[3 + a];
-    }
-    r[6] = part[b * 7 + 6] > r[6] ? part[b * 7 + 6] : r[6];
-  }
+__device__ __forceinline__ void block_fold7(double (&r)[7], double* out) {
   __shared__ double s[kThreads / kWave][7];
   const int w = threadIdx.x / kWave;
   for (int a = 0; a < 3; ++a) {
@@ -95,31 +55,74 @@ __global__ __launch_bounds__(kThreads) void k_bbox_final(const double* __restric
   }
 }
 
+__global__ __launch_bounds__(kThreads) void k_bbox_chunks(const double* __restrict__ xyz,
+                                                          const Chunk* __restrict__ chunks,
+                                                          double* __restrict__ part) {
+  const Chunk c = chunks[blockIdx.x];
+  double r[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0};
+  for (int64_t p = c.begin + threadIdx.x; p < c.end; p += kThreads) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double v = xyz[p * 3 + a];
+      if (!isfinite(v)) r[6] = 1.0;
+      r[a] = v < r[a] ? v : r[a];
+      r[3 + a] = v > r[3 + a] ? v : r[3 + a];
+    }
+  }
+  block_fold7(r, part + (int64_t)blockIdx.x * 7);
+}
+
+// block t folds chunks [cfirst[t], cfirst[t+1])
+__global__ __launch_bounds__(kThreads) void k_bbox_tiles(const double* __restrict__ part,
+                                                         const int32_t* __restrict__ cfirst,
+                                                         double* __restrict__ out) {
+  const int t = blockIdx.x;
+  double r[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0};
+  for (int b = cfirst[t] + threadIdx.x; b < cfirst[t + 1]; b += kThreads) {
+    for (int a = 0; a < 3; ++a) {
+      r[a] = part[b * 7 + a] < r[a] ? part[b * 7 + a] : r[a];
+      r[3 + a] = part[b * 7 + 3 + a] > r[3 + a] ? part[b * 7 + 3 + a] : r[3 + a];
+    }
+    r[6] = part[b * 7 + 6] > r[6] ? part[b * 7 + 6] : r[6];
+  }
+  block_fold7(r, out + (int64_t)t * 7);
+}
+
 // ---------------------------------------------------------------- keys
-struct KeyArgs {
-  double origin[3];
-  double s[3];
-  int64_t n[3];
-  int32_t dims;
-};
+// Tile of input point p: binary search over the tile offsets.
+__device__ __forceinline__ int tile_of(const int64_t* __restrict__ toff, int ntiles, int64_t p) {
+  int lo = 0, hi = ntiles - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (toff[mid] <= p)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
 
 template <class K>
 __global__ __launch_bounds__(kThreads) void k_keys(const double* __restrict__ xyz, int64_t n,
-                                                   KeyArgs ka, K* __restrict__ keys,
-                                                   uint32_t* __restrict__ vals,
+                                                   const Grid* __restrict__ tiles,
+                                                   const double* __restrict__ origin,
+                                                   const int64_t* __restrict__ toff, int ntiles,
+                                                   K* __restrict__ keys, uint32_t* __restrict__ vals,
                                                    float4* __restrict__ xyz4) {
   const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (p >= n) return;
+  const int t = ntiles > 1 ? tile_of(toff, ntiles, p) : 0;
+  const Grid g = tiles[t];
   float c[3];
   int64_t v[3] = {0, 0, 0};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    c[a] = (float)(xyz[p * 3 + a] - ka.origin[a]);  // FP64 recentring, then FP32
-    if (a < ka.dims) v[a] = voxel_clamped((double)c[a], ka.s[a], ka.n[a]);
+    c[a] = (float)(xyz[p * 3 + a] - origin[t * 3 + a]);  // FP64 recentring, then FP32
+    if (a < g.dims) v[a] = voxel_clamped((double)c[a], g.s[a], g.n[a]);
   }
-  const uint64_t g = ((uint64_t)v[0] * (uint64_t)ka.n[1] + (uint64_t)v[1]) * (uint64_t)ka.n[2] +
-                     (uint64_t)v[2];
-  keys[p] = (K)g;
+  const uint64_t key =
+      g.koff + ((uint64_t)v[0] * (uint64_t)g.n[1] + (uint64_t)v[1]) * (uint64_t)g.n[2] + (uint64_t)v[2];
+  keys[p] = (K)key;
   vals[p] = (uint32_t)p;
   xyz4[p] = make_float4(c[0], c[1], c[2], __int_as_float((int)p));
 }
@@ -256,20 +259,7 @@ __global__ __launch_bounds__(kThreads) void k_mixed_place(const uint64_t* __rest
 }
 
 // ---------------------------------------------------------------- host side
-static chs_status validate(const double* xyz, int64_t n, const chs_build_params* p,
-                           chs_index* out) {
-  if (!out) {
-    set_error("out is NULL");
-    return CHS_E_INVALID;
-  }
-  if (!xyz || !p) {
-    set_error("xyz or params is NULL");
-    return CHS_E_INVALID;
-  }
-  if (n < 1 || n > (int64_t)INT32_MAX) {
-    set_error("n = %lld outside [1, 2^31 - 1]", (long long)n);
-    return CHS_E_INVALID;
-  }
+static chs_status validate_params(const chs_build_params* p) {
   if (p->flavor < CHS_DENSE || p->flavor > CHS_MIXED) {
     set_error("unknown flavor %d", p->flavor);
     return CHS_E_INVALID;
@@ -294,9 +284,26 @@ static chs_status validate(const double* xyz, int64_t n, const chs_build_params*
   return CHS_OK;
 }
 
+static chs_status validate(const double* xyz, int64_t n, const chs_build_params* p,
+                           chs_index* out) {
+  if (!out) {
+    set_error("out is NULL");
+    return CHS_E_INVALID;
+  }
+  if (!xyz || !p) {
+    set_error("xyz or params is NULL");
+    return CHS_E_INVALID;
+  }
+  if (n < 1 || n > (int64_t)INT32_MAX) {
+    set_error("n = %lld outside [1, 2^31 - 1]", (long long)n);
+    return CHS_E_INVALID;
+  }
+  return validate_params(p);
+}
+
 template <class K>
-static chs_status build_sorted(chs_index ix, const double* xyz, int64_t n, const KeyArgs& ka,
-                               int bits) {
+static chs_status build_sorted(chs_index ix, const double* xyz, int64_t n, const double* origin_d,
+                               const int64_t* toff_d, int bits) {
   const Alloc& al = ix->al;
   hipStream_t st = al.stream;
   Buf keys(&al), vals(&al), tk(&al), tv(&al), xyz4(&al);
@@ -305,8 +312,8 @@ static chs_status build_sorted(chs_index ix, const double* xyz, int64_t n, const
   CHS_TRY(tk.alloc(sizeof(K) * n));
   CHS_TRY(tv.alloc(sizeof(uint32_t) * n));
   CHS_TRY(xyz4.alloc(sizeof(float4) * n));
-  k_keys<K><<<grid_for(n), kThreads, 0, st>>>(xyz, n, ka, keys.as<K>(), vals.as<uint32_t>(),
-                                              xyz4.as<float4>());
+  k_keys<K><<<grid_for(n), kThreads, 0, st>>>(xyz, n, ix->tiles_d, origin_d, toff_d, ix->ntiles,
+                                              keys.as<K>(), vals.as<uint32_t>(), xyz4.as<float4>());
   CHS_LAUNCH_CHECK();
   if (sizeof(K) == 4)
     CHS_TRY(radix_sort_u32(al, (uint32_t*)keys.p, vals.as<uint32_t>(), (uint32_t*)tk.p,
@@ -347,7 +354,7 @@ static chs_status build_sorted(chs_index ix, const double* xyz, int64_t n, const
 static chs_status build_dense(chs_index ix) {
   const Alloc& al = ix->al;
   hipStream_t st = al.stream;
-  const int64_t nc = (int64_t)ix->ncells;
+  const int64_t nc = (int64_t)ix->total_cells;
   Buf cnt(&al);
   CHS_TRY(cnt.alloc(sizeof(int32_t) * nc));
   k_fill_i32<<<4096, kThreads, 0, st>>>(cnt.as<int32_t>(), nc, 0);
@@ -382,7 +389,8 @@ static chs_status build_sparse(chs_index ix) {
 static chs_status build_mixed(chs_index ix) {
   const Alloc& al = ix->al;
   hipStream_t st = al.stream;
-  const int64_t nz = ix->ncell[2], nxy = ix->ncell[0] * ix->ncell[1];
+  const Grid& g = ix->grid();
+  const int64_t nz = g.n[2], nxy = g.n[0] * g.n[1];
   Buf cnt(&al);
   CHS_TRY(cnt.alloc(sizeof(int32_t) * nz));
   k_fill_i32<<<grid_for(nz), kThreads, 0, st>>>(cnt.as<int32_t>(), nz, 0);
@@ -426,79 +434,148 @@ static chs_status build_mixed(chs_index ix) {
   return CHS_OK;
 }
 
-static chs_status build_impl(chs_index ix, const double* xyz, int64_t n) {
+// Build over ntiles tiles (a plain index is one tile).  params[t] gives the
+// voxel edges and dims of tile t; the flavor is that of params[0].
+static chs_status build_impl(chs_index ix, const double* xyz, int64_t n, const int64_t* toff,
+                             int ntiles, const chs_build_params* params) {
   const Alloc& al = ix->al;
   hipStream_t st = al.stream;
-  // Eq. 1-2: bounding box (FP64) and a non-finite check
-  Buf part(&al), bb(&al);
-  CHS_TRY(part.alloc(sizeof(double) * 7 * kBoxBlocks));
-  CHS_TRY(bb.alloc(sizeof(double) * 7));
-  int nb = (int)((n + kThreads - 1) / kThreads);
-  if (nb > kBoxBlocks) nb = kBoxBlocks;
-  k_bbox<<<nb, kThreads, 0, st>>>(xyz, n, part.as<double>());
+  ix->ntiles = ntiles;
+  ix->tile_off.assign(toff, toff + ntiles + 1);
+  // chunks of at most kBoxChunk points, never straddling two tiles
+  std::vector<Chunk> chunks;
+  std::vector<int32_t> cfirst(ntiles + 1, 0);
+  for (int t = 0; t < ntiles; ++t) {
+    cfirst[t] = (int32_t)chunks.size();
+    for (int64_t b = toff[t]; b < toff[t + 1]; b += kBoxChunk)
+      chunks.push_back(Chunk{b, b + kBoxChunk < toff[t + 1] ? b + kBoxChunk : toff[t + 1]});
+  }
+  cfirst[ntiles] = (int32_t)chunks.size();
+  Buf chunk_d(&al), cfirst_d(&al), part(&al), bb(&al), toff_d(&al), origin_d(&al);
+  CHS_TRY(chunk_d.alloc(sizeof(Chunk) * chunks.size()));
+  CHS_TRY(cfirst_d.alloc(sizeof(int32_t) * (ntiles + 1)));
+  CHS_TRY(part.alloc(sizeof(double) * 7 * chunks.size()));
+  CHS_TRY(bb.alloc(sizeof(double) * 7 * ntiles));
+  CHS_HIP(hipMemcpyAsync(chunk_d.p, chunks.data(), sizeof(Chunk) * chunks.size(),
+                         hipMemcpyHostToDevice, st));
+  CHS_HIP(hipMemcpyAsync(cfirst_d.p, cfirst.data(), sizeof(int32_t) * (ntiles + 1),
+                         hipMemcpyHostToDevice, st));
+  k_bbox_chunks<<<(unsigned)chunks.size(), kThreads, 0, st>>>(xyz, chunk_d.as<Chunk>(),
+                                                               part.as<double>());
   CHS_LAUNCH_CHECK();
-  k_bbox_final<<<1, kThreads, 0, st>>>(part.as<double>(), nb, bb.as<double>());
+  k_bbox_tiles<<<(unsigned)ntiles, kThreads, 0, st>>>(part.as<double>(), cfirst_d.as<int32_t>(),
+                                                       bb.as<double>());
   CHS_LAUNCH_CHECK();
-  double h[7];
-  CHS_HIP(hipMemcpyAsync(h, bb.p, sizeof(h), hipMemcpyDeviceToHost, st));
+  std::vector<double> h(7 * (size_t)ntiles);
+  CHS_HIP(hipMemcpyAsync(h.data(), bb.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
   CHS_HIP(hipStreamSynchronize(st));
-  if (h[6] != 0.0) {
-    set_error("xyz holds non-finite coordinates");
-    return CHS_E_INVALID;
-  }
-  for (int a = 0; a < 3; ++a) {
-    ix->origin[a] = h[a];
-    // recentring is monotone, so the FP32 maximum is fl32(max - min)
-    ix->max32[a] = (float)(h[3 + a] - h[a]);
-  }
-  // Eq. 3: n_a = floor((p+_a - p-_a) / s_a) + 1; 2D indexing keeps one z voxel
-  double prod = 1.0;
-  for (int a = 0; a < 3; ++a) {
-    if (a == 2 && ix->dims == 2) {
-      ix->ncell[2] = 1;
-      continue;
+  ix->tiles.resize(ntiles);
+  ix->origin.resize(3 * (size_t)ntiles);
+  ix->max32.resize(3 * (size_t)ntiles);
+  uint64_t koff = 0;
+  for (int t = 0; t < ntiles; ++t) {
+    const double* r = &h[7 * (size_t)t];
+    if (r[6] != 0.0) {
+      set_error("xyz holds non-finite coordinates (tile %d)", t);
+      return CHS_E_INVALID;
     }
-    const double na = std::floor((double)ix->max32[a] / ix->cell[a]) + 1.0;
-    if (!(na < 4.0e18)) {
-      set_error("grid axis %d would have %g voxels", a, na);
+    const chs_build_params& p = params[t];
+    Grid& g = ix->tiles[t];
+    g.dims = p.dims;
+    g.pad_ = 0;
+    g.poff = toff[t];
+    g.koff = koff;
+    double prod = 1.0;
+    for (int a = 0; a < 3; ++a) {
+      ix->origin[3 * t + a] = r[a];
+      // recentring is monotone, so the FP32 maximum is fl32(max - min)
+      ix->max32[3 * t + a] = (float)(r[3 + a] - r[a]);
+      g.s[a] = (a == 2 && p.dims == 2) ? 1.0 : p.cell[a];
+      if (a == 2 && p.dims == 2) {
+        g.n[2] = 1;
+        continue;
+      }
+      // Eq. 3: n_a = floor((p+_a - p-_a) / s_a) + 1
+      const double na = std::floor((double)ix->max32[3 * t + a] / g.s[a]) + 1.0;
+      if (!(na < 1.0e9)) {
+        set_error("tile %d: grid axis %d would have %g voxels", t, a, na);
+        return CHS_E_CAPACITY;
+      }
+      g.n[a] = (int64_t)na;
+      prod *= na;
+    }
+    if (!(prod + (double)koff < 4.0e18)) {
+      set_error("grid would have %g voxels (global index overflows 64 bits)", prod + (double)koff);
       return CHS_E_CAPACITY;
     }
-    ix->ncell[a] = (int64_t)na;
-    prod *= na;
+    koff += (uint64_t)g.n[0] * (uint64_t)g.n[1] * (uint64_t)g.n[2];
   }
-  if (!(prod < 9.0e18)) {
-    set_error("grid would have %g voxels (global index overflows 64 bits)", prod);
+  ix->total_cells = koff;
+  if (ix->flavor == CHS_DENSE && ix->total_cells > (uint64_t)ix->ncells_limit()) {
+    set_error("dense grid of %llu voxels exceeds the limit %lld; use the sparse or mixed flavor",
+              (unsigned long long)ix->total_cells, (long long)ix->ncells_limit());
     return CHS_E_CAPACITY;
   }
-  ix->ncells = (uint64_t)ix->ncell[0] * (uint64_t)ix->ncell[1] * (uint64_t)ix->ncell[2];
-  if (ix->flavor == CHS_DENSE) {
-    if (ix->ncells > (uint64_t)ix->ncells_limit()) {
-      set_error("dense grid of %llu voxels exceeds the limit %lld; use the sparse or mixed flavor",
-                (unsigned long long)ix->ncells, (long long)ix->ncells_limit());
-      return CHS_E_CAPACITY;
-    }
-  }
-  if (ix->flavor == CHS_MIXED &&
-      (double)ix->ncell[0] * (double)ix->ncell[1] > 2.0e9) {
+  if (ix->flavor == CHS_MIXED && (double)ix->grid().n[0] * (double)ix->grid().n[1] > 2.0e9) {
     set_error("mixed flavor: a z-slice of %lld x %lld voxels is too large",
-              (long long)ix->ncell[0], (long long)ix->ncell[1]);
+              (long long)ix->grid().n[0], (long long)ix->grid().n[1]);
     return CHS_E_CAPACITY;
   }
-  KeyArgs ka;
-  for (int a = 0; a < 3; ++a) {
-    ka.origin[a] = ix->origin[a];
-    ka.s[a] = ix->cell[a];
-    ka.n[a] = ix->ncell[a];
-  }
-  ka.dims = ix->dims;
-  const int bits = ceil_log2(ix->ncells);
+  CHS_TRY(ix->own(&ix->tiles_d, (size_t)ntiles));
+  CHS_HIP(hipMemcpyAsync(ix->tiles_d, ix->tiles.data(), sizeof(Grid) * ntiles,
+                         hipMemcpyHostToDevice, st));
+  CHS_TRY(toff_d.alloc(sizeof(int64_t) * (ntiles + 1)));
+  CHS_TRY(origin_d.alloc(sizeof(double) * 3 * ntiles));
+  CHS_HIP(hipMemcpyAsync(toff_d.p, toff, sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice, st));
+  CHS_HIP(hipMemcpyAsync(origin_d.p, ix->origin.data(), sizeof(double) * 3 * ntiles,
+                         hipMemcpyHostToDevice, st));
+  const int bits = ceil_log2(ix->total_cells);
   if (bits <= 32)
-    CHS_TRY(build_sorted<uint32_t>(ix, xyz, n, ka, bits));
+    CHS_TRY(build_sorted<uint32_t>(ix, xyz, n, origin_d.as<double>(), toff_d.as<int64_t>(), bits));
   else
-    CHS_TRY(build_sorted<uint64_t>(ix, xyz, n, ka, bits));
+    CHS_TRY(build_sorted<uint64_t>(ix, xyz, n, origin_d.as<double>(), toff_d.as<int64_t>(), bits));
   if (ix->flavor == CHS_DENSE) CHS_TRY(build_dense(ix));
   if (ix->flavor == CHS_SPARSE) CHS_TRY(build_sparse(ix));
   if (ix->flavor == CHS_MIXED) CHS_TRY(build_mixed(ix));
+  // ukeys, ustart, the tile table and the host vectors above are in use
+  // by queued work; wait before they go out of scope
+  CHS_HIP(hipStreamSynchronize(st));
+  return CHS_OK;
+}
+
+static chs_status build_common(const double* xyz, int64_t n, const int64_t* toff, int ntiles,
+                               const chs_build_params* params, const chs_allocator* alloc,
+                               hipStream_t stream, chs_index* out) {
+  if (alloc && (!alloc->alloc || !alloc->free)) {
+    set_error("allocator callbacks are NULL");
+    return CHS_E_INVALID;
+  }
+  chs_index ix = new chs_index_s();
+  ix->al.stream = stream;
+  if (alloc) {
+    ix->al.a = *alloc;
+    ix->al.has = true;
+  }
+  ix->flavor = params[0].flavor;
+  ix->mixed_pct = params[0].mixed_dense_pct > 0 ? params[0].mixed_dense_pct : 80;
+  ix->max_dense =
+      params[0].max_dense_cells > 0 ? params[0].max_dense_cells : (int64_t)INT32_MAX - 1;
+  ix->n = n;
+  ix->persistent = ntiles > 1;
+  if (hipGetDevice(&ix->device) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("no HIP device");
+    delete ix;
+    return CHS_E_DEVICE;
+  }
+  chs_status s = build_impl(ix, xyz, n, toff, ntiles, params);
+  if (s != CHS_OK) {
+    std::string msg = last_error();
+    chs_free(ix);
+    set_error("%s", msg.c_str());
+    return s;
+  }
+  *out = ix;
   return CHS_OK;
 }
 
@@ -510,38 +587,40 @@ extern "C" chs_status chs_build(const double* xyz, int64_t n, const chs_build_pa
                                 const chs_allocator* alloc, hipStream_t stream, chs_index* out) {
   clear_error();
   CHS_TRY(validate(xyz, n, params, out));
-  if (alloc && (!alloc->alloc || !alloc->free)) {
-    set_error("allocator callbacks are NULL");
+  const int64_t toff[2] = {0, n};
+  return build_common(xyz, n, toff, 1, params, alloc, stream, out);
+}
+
+extern "C" chs_status chs_build_batch(const double* xyz, int64_t n, const int64_t* tile_off,
+                                      int32_t ntiles, const chs_build_params* params,
+                                      const chs_allocator* alloc, hipStream_t stream,
+                                      chs_index* out) {
+  clear_error();
+  CHS_TRY(validate(xyz, n, params, out));
+  if (!tile_off || ntiles < 1 || ntiles > (1 << 20)) {
+    set_error("tile_off is NULL or ntiles = %d outside [1, 2^20]", ntiles);
     return CHS_E_INVALID;
   }
-  chs_index ix = new chs_index_s();
-  ix->al.stream = stream;
-  if (alloc) {
-    ix->al.a = *alloc;
-    ix->al.has = true;
+  if (tile_off[0] != 0 || tile_off[ntiles] != n) {
+    set_error("tile_off must start at 0 and end at n");
+    return CHS_E_INVALID;
   }
-  ix->flavor = params->flavor;
-  ix->dims = params->dims;
-  ix->mixed_pct = params->mixed_dense_pct > 0 ? params->mixed_dense_pct : 80;
-  ix->max_dense = params->max_dense_cells > 0 ? params->max_dense_cells : (int64_t)INT32_MAX - 1;
-  for (int a = 0; a < 3; ++a) ix->cell[a] = params->cell[a];
-  if (ix->dims == 2) ix->cell[2] = 1.0;
-  ix->n = n;
-  if (hipGetDevice(&ix->device) != hipSuccess) {
-    (void)hipGetLastError();
-    set_error("no HIP device");
-    delete ix;
-    return CHS_E_DEVICE;
+  for (int t = 0; t < ntiles; ++t) {
+    if (tile_off[t + 1] <= tile_off[t]) {
+      set_error("tile %d is empty or tile_off decreases", t);
+      return CHS_E_INVALID;
+    }
+    CHS_TRY(validate_params(&params[t]));
+    if (params[t].flavor != params[0].flavor) {
+      set_error("all tiles must use the same flavor");
+      return CHS_E_INVALID;
+    }
   }
-  chs_status s = build_impl(ix, xyz, n);
-  if (s != CHS_OK) {
-    std::string msg = last_error();
-    chs_free(ix);
-    set_error("%s", msg.c_str());
-    return s;
+  if (ntiles > 1 && params[0].flavor == CHS_MIXED) {
+    set_error("the mixed flavor is not available for batched indexes");
+    return CHS_E_UNSUPPORTED;
   }
-  *out = ix;
-  return CHS_OK;
+  return build_common(xyz, n, tile_off, ntiles, params, alloc, stream, out);
 }
 
 extern "C" void chs_free(chs_index ix) {
@@ -551,25 +630,59 @@ extern "C" void chs_free(chs_index ix) {
   delete ix;
 }
 
+extern "C" chs_status chs_index_set_option(chs_index ix, int32_t option, int64_t value) {
+  clear_error();
+  if (!ix) {
+    set_error("index is NULL");
+    return CHS_E_INVALID;
+  }
+  if (option == CHS_OPT_PERSISTENT) {
+    ix->persistent = value != 0;
+    return CHS_OK;
+  }
+  set_error("unknown option %d", option);
+  return CHS_E_INVALID;
+}
+
+static void fill_info(chs_index ix, int t, chs_index_info_t* out) {
+  std::memset(out, 0, sizeof(*out));
+  const Grid& g = ix->tiles[t];
+  for (int a = 0; a < 3; ++a) {
+    out->origin[a] = ix->origin[3 * t + a];
+    out->max32[a] = ix->max32[3 * t + a];
+    out->cell[a] = g.s[a];
+    out->ncell[a] = g.n[a];
+  }
+  out->dims = g.dims;
+  out->flavor = ix->flavor;
+}
+
 extern "C" chs_status chs_index_info(chs_index ix, chs_index_info_t* out) {
   clear_error();
   if (!ix || !out) {
     set_error("index or out is NULL");
     return CHS_E_INVALID;
   }
-  std::memset(out, 0, sizeof(*out));
-  for (int a = 0; a < 3; ++a) {
-    out->origin[a] = ix->origin[a];
-    out->max32[a] = ix->max32[a];
-    out->cell[a] = ix->cell[a];
-    out->ncell[a] = ix->ncell[a];
-  }
+  fill_info(ix, 0, out);
   out->n_points = ix->n;
   out->n_nonempty = ix->M;
   out->n_dense_slices = ix->n_dense_slices;
   out->device_bytes = ix->device_bytes;
-  out->flavor = ix->flavor;
-  out->dims = ix->dims;
+  out->ntiles = ix->ntiles;
+  return CHS_OK;
+}
+
+extern "C" chs_status chs_tile_info(chs_index ix, int32_t tile, chs_index_info_t* out) {
+  clear_error();
+  if (!ix || !out || tile < 0 || tile >= ix->ntiles) {
+    set_error("index or out is NULL, or tile out of range");
+    return CHS_E_INVALID;
+  }
+  fill_info(ix, tile, out);
+  out->n_points = ix->tile_off[tile + 1] - ix->tile_off[tile];
+  out->n_nonempty = -1;
+  out->device_bytes = ix->device_bytes;
+  out->ntiles = ix->ntiles;
   return CHS_OK;
 }
 

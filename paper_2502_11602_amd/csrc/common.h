@@ -71,17 +71,24 @@ struct Buf {
 };
 
 // ---------------------------------------------------------------- grid
-// Grid geometry as the kernels see it.
+// Geometry of one tile's grid as the kernels see it.  A plain index is one
+// tile; a batched index concatenates the tiles' voxel key spaces, tile t's
+// voxel (0,0,0) having the global key koff.
 struct Grid {
-  double s[3];   // voxel edges
-  int64_t n[3];  // n_x, n_y, n_z
+  double s[3];    // voxel edges
+  int64_t n[3];   // n_x, n_y, n_z
+  uint64_t koff;  // global key of the tile's first voxel
+  int64_t poff;   // first input point of the tile (results are tile-local)
   int32_t dims;
+  int32_t pad_;
 };
 
-// Voxel storage as the kernels see it.
+// Voxel storage as the kernels see it (global over all tiles).
 struct Voxels {
   int32_t flavor;
-  const int32_t* dstart;     // DENSE: [ncells+1]
+  int32_t M;                 // non-empty voxels
+  int64_t npts;              // stored points
+  const int32_t* dstart;     // DENSE: [total voxels + 1]
   const uint64_t* hkeys;     // SPARSE/MIXED: open-addressing keys (EMPTY = ~0)
   const int32_t* hvals;      //   -> compact voxel id
   uint64_t hmask;            //   capacity - 1 (power of two)
@@ -98,17 +105,21 @@ constexpr uint64_t kEmptyKey = ~0ull;
 struct chs_index_s {
   chs::Alloc al;
   int device = 0;
-  int32_t flavor = 0, dims = 3, mixed_pct = 80;
-  double cell[3] = {1, 1, 1};
-  double origin[3] = {0, 0, 0};
-  float max32[3] = {0, 0, 0};
-  int64_t ncell[3] = {1, 1, 1};
-  uint64_t ncells = 1;
+  int32_t flavor = 0, mixed_pct = 80;
+  int32_t ntiles = 1;
   int64_t n = 0, M = 0;
+  uint64_t total_cells = 1;  // voxels over all tiles
   int64_t n_dense_slices = 0;
   int64_t device_bytes = 0;
   int64_t max_dense = (int64_t)INT32_MAX - 1;
-  int64_t ncells_limit() const { return max_dense; }
+  bool persistent = false;  // searches pull waves from a work counter
+  // per tile, host copies (tile 0 is the whole cloud of a plain index)
+  std::vector<chs::Grid> tiles;
+  std::vector<double> origin;   // [3 * ntiles]
+  std::vector<float> max32;     // [3 * ntiles]
+  std::vector<int64_t> tile_off;  // [ntiles + 1] input point ranges
+  std::vector<int64_t> tile_m;    // non-empty voxels per tile
+  chs::Grid* tiles_d = nullptr;   // device copy of `tiles`
   // stored (voxel-ordered) cloud
   int32_t* perm = nullptr;
   int32_t* inv_perm = nullptr;
@@ -124,22 +135,23 @@ struct chs_index_s {
   uint8_t* slice_dense = nullptr;
   int64_t* slice_off = nullptr;
   int32_t* stab = nullptr;
-  // cached processing order for "every point" queries
+  // cached processing order for "every point" queries: centres in waves of
+  // at most 64 that never straddle two tiles
   float4* allq = nullptr;
+  int32_t* wave_tile = nullptr;   // batched only: tile of each wave
+  int32_t* wave_start = nullptr;  //   first query of each wave
+  int32_t* tile_qend = nullptr;   //   end of each tile's queries
+  int64_t allq_waves = 0;
+  int32_t* work_counter = nullptr;  // persistent launches
   std::vector<void*> owned;
 
-  chs::Grid grid() const {
-    chs::Grid g;
-    for (int a = 0; a < 3; ++a) {
-      g.s[a] = cell[a];
-      g.n[a] = ncell[a];
-    }
-    g.dims = dims;
-    return g;
-  }
+  int64_t ncells_limit() const { return max_dense; }
+  const chs::Grid& grid() const { return tiles[0]; }
   chs::Voxels voxels() const {
     chs::Voxels v;
     v.flavor = flavor;
+    v.M = (int32_t)M;
+    v.npts = n;
     v.dstart = dstart;
     v.hkeys = hkeys;
     v.hvals = hvals;
@@ -234,47 +246,70 @@ __device__ __forceinline__ int32_t hash_find(const uint64_t* __restrict__ hk,
   }
 }
 
-// Compact id of the non-empty voxel (i,j,k), or -1 if it holds no point.
+// Compact id of the non-empty voxel (i,j,k) of the tile, or -1 if it holds
+// no point.  The flavor FL is a compile-time constant: a run-time flavor
+// test inside the divergent probing loops below was once compiled into a
+// lane mask reused under a different exec mask, which sent sparse lookups
+// into the mixed flavor's slice table (a NULL pointer there).
+template <int FL>
 __device__ __forceinline__ int32_t voxel_id(const Voxels& vx, const Grid& g, int64_t i, int64_t j,
                                             int64_t k) {
-  const uint64_t key = ((uint64_t)i * (uint64_t)g.n[1] + (uint64_t)j) * (uint64_t)g.n[2] + (uint64_t)k;
-  if (vx.flavor == CHS_MIXED && vx.slice_dense[k])
-    return vx.stab[vx.slice_off[k] + i * g.n[1] + j];
-  return hash_find(vx.hkeys, vx.hvals, vx.hmask, key);
+  const uint64_t key =
+      g.koff + ((uint64_t)i * (uint64_t)g.n[1] + (uint64_t)j) * (uint64_t)g.n[2] + (uint64_t)k;
+  int32_t u;
+  if (FL == CHS_MIXED && vx.slice_dense[k]) {
+    const int64_t so = vx.slice_off[k];
+    u = so >= 0 ? vx.stab[so + i * g.n[1] + j] : -1;
+  } else {
+    u = hash_find(vx.hkeys, vx.hvals, vx.hmask, key);
+  }
+  return (u >= 0 && u < vx.M) ? u : -1;
 }
 
 // Stored-position range [b, e) of the voxels (i, j, k0..k1) of one column.
 // Because the global index is z-fastest (Eq. 7), these voxels are adjacent
-// in the stored order and their points form one contiguous run.
+// in the stored order and their points form one contiguous run.  Voxel
+// coordinates outside the tile give an empty run, and every table value is
+// checked against the table's extent before use.
+template <int FL>
 __device__ __forceinline__ void column_run(const Voxels& vx, const Grid& g, int64_t i, int64_t j,
                                            int64_t k0, int64_t k1, int32_t* b, int32_t* e) {
-  const uint64_t base = ((uint64_t)i * (uint64_t)g.n[1] + (uint64_t)j) * (uint64_t)g.n[2];
-  if (vx.flavor == CHS_DENSE) {
-    *b = vx.dstart[base + k0];
-    *e = vx.dstart[base + k1 + 1];
-    return;
-  }
-  int64_t k = k0;
-  int32_t u0 = -1;
-  for (; k <= k1; ++k) {
-    u0 = voxel_id(vx, g, i, j, k);
-    if (u0 >= 0) break;
-  }
-  if (u0 < 0) {
-    *b = 0;
-    *e = 0;
-    return;
-  }
-  int32_t u1 = u0;
-  for (int64_t kk = k1; kk > k; --kk) {
-    int32_t u = voxel_id(vx, g, i, j, kk);
-    if (u >= 0) {
-      u1 = u;
-      break;
+  *b = 0;
+  *e = 0;
+  if (k0 < 0) k0 = 0;
+  if (k1 > g.n[2] - 1) k1 = g.n[2] - 1;
+  if (i < 0 || i >= g.n[0] || j < 0 || j >= g.n[1] || k0 > k1) return;
+  const uint64_t base =
+      g.koff + ((uint64_t)i * (uint64_t)g.n[1] + (uint64_t)j) * (uint64_t)g.n[2];
+  int32_t rb, re;
+  if (FL == CHS_DENSE) {
+    rb = vx.dstart[base + k0];
+    re = vx.dstart[base + k1 + 1];
+  } else {
+    int64_t k = k0;
+    int32_t u0 = -1;
+    for (; k <= k1; ++k) {
+      u0 = voxel_id<FL>(vx, g, i, j, k);
+      if (u0 >= 0) break;
     }
+    if (u0 < 0) return;
+    int32_t u1 = u0;
+    for (int64_t kk = k1; kk > k; --kk) {
+      const int32_t u = voxel_id<FL>(vx, g, i, j, kk);
+      if (u >= 0) {
+        u1 = u;
+        break;
+      }
+    }
+    rb = vx.ustart[u0];
+    re = vx.ustart[u1 + 1];
   }
-  *b = vx.ustart[u0];
-  *e = vx.ustart[u1 + 1];
+  if (rb < 0) rb = 0;
+  if (re > vx.npts) re = (int32_t)vx.npts;
+  if (re > rb) {
+    *b = rb;
+    *e = re;
+  }
 }
 
 // Block index remapped so that consecutive logical blocks run on the same
@@ -334,6 +369,10 @@ struct QueryPlan {
   Buf q4;
   const float4* q = nullptr;
   int64_t nq = 0;
+  int64_t nwaves = 0;
+  const int32_t* wave_tile = nullptr;   // batched: tile, first query of each wave
+  const int32_t* wave_start = nullptr;
+  const int32_t* tile_qend = nullptr;   //   and the end of each tile's queries
   explicit QueryPlan(const Alloc* al) : q4(al) {}
 };
 chs_status plan_queries(chs_index ix, const chs_queries* qs, QueryPlan* plan, hipStream_t stream);

@@ -12,6 +12,7 @@
 // fetched once per wave through the scalar unit and compared against the 64
 // queries held in the lanes: no per-lane gathers, no LDS, and the distance
 // arithmetic is the unfused FP32 definition.
+#include <algorithm>
 #include <cmath>
 
 #include "common.h"
@@ -33,52 +34,73 @@ static unsigned grid_for(int64_t n, int per_block = kThreads) {
 }
 
 // ---------------------------------------------------------------- query planning
-struct PlanArgs {
-  double origin[3];
-  Grid g;
-  int m;       // Hilbert order (bits per axis)
-  int kbits;   // bits of the z voxel index
+// Per tile: Hilbert order m (bits per axis), bits of the z voxel index, and
+// the tile's processing rank (largest tiles first).
+struct TilePlan {
+  int32_t m, kbits, rank, pad_;
 };
 
+__device__ __forceinline__ int tile_of_point(const int64_t* __restrict__ toff, int ntiles, int64_t p) {
+  int lo = 0, hi = ntiles - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (toff[mid] <= p)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 // Per query: recentred FP32 centre (invalid queries are flagged) and the
-// ordering key hilbert(i, j) << kbits | k.
+// ordering key rank << lshift | hilbert(i, j) << kbits | k.
 template <class K>
 __global__ __launch_bounds__(kThreads) void k_plan_keys(
     int mode, const double* __restrict__ xyz, const int32_t* __restrict__ pidx, int64_t nq,
     const float4* __restrict__ pts, const int32_t* __restrict__ inv_perm,
-    const int32_t* __restrict__ perm, int64_t npts, PlanArgs pa, K* __restrict__ keys,
+    const int32_t* __restrict__ perm, int64_t npts, const Grid* __restrict__ tiles,
+    const TilePlan* __restrict__ tplan, const int64_t* __restrict__ toff, int ntiles,
+    double ox, double oy, double oz, int lshift, int total_bits, K* __restrict__ keys,
     uint32_t* __restrict__ vals, float4* __restrict__ tmp) {
   const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (q >= nq) return;
   float4 c;
   bool ok = true;
   uint32_t caller = (uint32_t)q;
+  int t = 0;
   if (mode == 0) {  // every point, walked in stored order
     c = pts[q];
     caller = (uint32_t)perm[q];
-  } else if (mode == 1) {  // point indices
+    if (ntiles > 1) t = tile_of_point(toff, ntiles, (int64_t)caller);
+  } else if (mode == 1) {  // point indices (single tile)
     const int32_t p = pidx[q];
     ok = p >= 0 && (int64_t)p < npts;
     c = ok ? pts[inv_perm[p]] : make_float4(0.f, 0.f, 0.f, 0.f);
-  } else {  // FP64 coordinates
+  } else {  // FP64 coordinates (single tile)
+    const double o[3] = {ox, oy, oz};
     float v[3];
     for (int a = 0; a < 3; ++a) {
       const double x = xyz[q * 3 + a];
       ok = ok && isfinite(x);
-      v[a] = (float)(x - pa.origin[a]);
+      v[a] = (float)(x - o[a]);
     }
     if (!ok) v[0] = v[1] = v[2] = 0.f;
     c = make_float4(v[0], v[1], v[2], 0.f);
   }
+  const Grid g = tiles[t];
+  const TilePlan tp = tplan[t];
   int64_t cell[3] = {0, 0, 0};
   const float cc[3] = {c.x, c.y, c.z};
-  for (int a = 0; a < pa.g.dims; ++a) cell[a] = voxel_clamped((double)cc[a], pa.g.s[a], pa.g.n[a]);
-  const int total = 2 * pa.m + pa.kbits;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    if (a < g.dims) cell[a] = voxel_clamped((double)cc[a], g.s[a], g.n[a]);
   K key;
   if (ok) {
-    key = (K)((hilbert2((uint32_t)cell[0], (uint32_t)cell[1], pa.m) << pa.kbits) | (uint64_t)cell[2]);
+    const uint64_t local =
+        (hilbert2((uint32_t)cell[0], (uint32_t)cell[1], tp.m) << tp.kbits) | (uint64_t)cell[2];
+    key = (K)(((uint64_t)tp.rank << lshift) | local);
   } else {
-    key = (K)(total >= 64 ? ~0ull : ((1ull << total) - 1));
+    key = (K)(total_bits >= 64 ? ~0ull : ((1ull << total_bits) - 1));
   }
   keys[q] = key;
   vals[q] = (uint32_t)q;
@@ -95,17 +117,28 @@ __global__ __launch_bounds__(kThreads) void k_plan_gather(const uint32_t* __rest
 }
 
 static chs_status plan_impl(chs_index ix, int mode, const double* xyz, const int32_t* pidx,
-                            int64_t nq, float4* q4, hipStream_t st) {
+                            int64_t nq, const std::vector<int32_t>& rank, float4* q4,
+                            hipStream_t st) {
   Alloc al = ix->al;
   al.stream = st;
-  PlanArgs pa;
-  for (int a = 0; a < 3; ++a) pa.origin[a] = ix->origin[a];
-  pa.g = ix->grid();
-  int64_t nmax = ix->ncell[0] > ix->ncell[1] ? ix->ncell[0] : ix->ncell[1];
-  pa.m = ceil_log2((uint64_t)nmax);
-  pa.kbits = ceil_log2((uint64_t)ix->ncell[2]);
-  const int bits = 2 * pa.m + pa.kbits;
-  Buf keys(&al), vals(&al), tk(&al), tv(&al), tmp(&al);
+  const int T = ix->ntiles;
+  std::vector<TilePlan> tp(T);
+  int lshift = 0;
+  for (int t = 0; t < T; ++t) {
+    const Grid& g = ix->tiles[t];
+    tp[t].m = ceil_log2((uint64_t)(g.n[0] > g.n[1] ? g.n[0] : g.n[1]));
+    tp[t].kbits = ceil_log2((uint64_t)g.n[2]);
+    tp[t].rank = rank[t];
+    tp[t].pad_ = 0;
+    const int lb = 2 * tp[t].m + tp[t].kbits;
+    lshift = lb > lshift ? lb : lshift;
+  }
+  const int bits = lshift + (T > 1 ? ceil_log2((uint64_t)T) : 0);
+  if (bits > 64) {
+    set_error("query ordering key would need %d bits", bits);
+    return CHS_E_CAPACITY;
+  }
+  Buf keys(&al), vals(&al), tk(&al), tv(&al), tmp(&al), tp_d(&al), toff_d(&al);
   const bool wide = bits > 32;
   const size_t ks = wide ? 8 : 4;
   CHS_TRY(keys.alloc(ks * nq));
@@ -113,23 +146,33 @@ static chs_status plan_impl(chs_index ix, int mode, const double* xyz, const int
   CHS_TRY(vals.alloc(4 * nq));
   CHS_TRY(tv.alloc(4 * nq));
   CHS_TRY(tmp.alloc(sizeof(float4) * nq));
+  CHS_TRY(tp_d.alloc(sizeof(TilePlan) * T));
+  CHS_TRY(toff_d.alloc(sizeof(int64_t) * (T + 1)));
+  CHS_HIP(hipMemcpyAsync(tp_d.p, tp.data(), sizeof(TilePlan) * T, hipMemcpyHostToDevice, st));
+  CHS_HIP(hipMemcpyAsync(toff_d.p, ix->tile_off.data(), sizeof(int64_t) * (T + 1),
+                         hipMemcpyHostToDevice, st));
+  const double* o = ix->origin.data();
   if (wide) {
     k_plan_keys<uint64_t><<<grid_for(nq), kThreads, 0, st>>>(
-        mode, xyz, pidx, nq, ix->pts, ix->inv_perm, ix->perm, ix->n, pa, keys.as<uint64_t>(),
-        vals.as<uint32_t>(), tmp.as<float4>());
+        mode, xyz, pidx, nq, ix->pts, ix->inv_perm, ix->perm, ix->n, ix->tiles_d,
+        tp_d.as<TilePlan>(), toff_d.as<int64_t>(), T, o[0], o[1], o[2], lshift, bits,
+        keys.as<uint64_t>(), vals.as<uint32_t>(), tmp.as<float4>());
     CHS_LAUNCH_CHECK();
     CHS_TRY(radix_sort_u64(al, keys.as<uint64_t>(), vals.as<uint32_t>(), tk.as<uint64_t>(),
                            tv.as<uint32_t>(), nq, bits));
   } else {
     k_plan_keys<uint32_t><<<grid_for(nq), kThreads, 0, st>>>(
-        mode, xyz, pidx, nq, ix->pts, ix->inv_perm, ix->perm, ix->n, pa, keys.as<uint32_t>(),
-        vals.as<uint32_t>(), tmp.as<float4>());
+        mode, xyz, pidx, nq, ix->pts, ix->inv_perm, ix->perm, ix->n, ix->tiles_d,
+        tp_d.as<TilePlan>(), toff_d.as<int64_t>(), T, o[0], o[1], o[2], lshift, bits,
+        keys.as<uint32_t>(), vals.as<uint32_t>(), tmp.as<float4>());
     CHS_LAUNCH_CHECK();
     CHS_TRY(radix_sort_u32(al, keys.as<uint32_t>(), vals.as<uint32_t>(), tk.as<uint32_t>(),
                            tv.as<uint32_t>(), nq, bits));
   }
   k_plan_gather<<<grid_for(nq), kThreads, 0, st>>>(vals.as<uint32_t>(), tmp.as<float4>(), nq, q4);
   CHS_LAUNCH_CHECK();
+  // tp and toff copies were queued from host vectors that die here
+  CHS_HIP(hipStreamSynchronize(st));
   return CHS_OK;
 }
 
@@ -151,31 +194,125 @@ static chs_status check_queries(chs_index ix, const chs_queries* qs) {
               (long long)ix->n);
     return CHS_E_INVALID;
   }
+  if (ix->ntiles > 1 && qs->nq != 0 && (qs->xyz || qs->point_idx)) {
+    set_error("a batched index answers \"every point\" queries only");
+    return CHS_E_UNSUPPORTED;
+  }
   return CHS_OK;
 }
 
 chs_status plan_queries(chs_index ix, const chs_queries* qs, QueryPlan* plan, hipStream_t st) {
   plan->nq = qs->nq;
+  plan->wave_tile = nullptr;
+  plan->wave_start = nullptr;
+  plan->tile_qend = nullptr;
+  plan->nwaves = (qs->nq + kWave - 1) / kWave;
   if (qs->nq == 0) return CHS_OK;
+  const int T = ix->ntiles;
   if (!qs->xyz && !qs->point_idx) {
     if (!ix->allq) {
       // cached on the index: the order of "every point" queries never changes
-      Alloc al = ix->al;
+      std::vector<int64_t> order(T);
+      for (int t = 0; t < T; ++t) order[t] = t;
+      std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        return ix->tile_off[a + 1] - ix->tile_off[a] > ix->tile_off[b + 1] - ix->tile_off[b];
+      });
+      std::vector<int32_t> rank(T);
+      for (int r = 0; r < T; ++r) rank[order[r]] = r;
       float4* a = nullptr;
       CHS_TRY(ix->own(&a, (size_t)ix->n));
-      chs_status s = plan_impl(ix, 0, nullptr, nullptr, ix->n, a, st);
-      if (s != CHS_OK) return s;
+      CHS_TRY(plan_impl(ix, 0, nullptr, nullptr, ix->n, rank, a, st));
+      if (T > 1) {
+        // waves of at most 64 queries that stay inside one tile
+        std::vector<int32_t> wtile, wstart, qend(T);
+        int64_t pos = 0;
+        for (int r = 0; r < T; ++r) {
+          const int t = (int)order[r];
+          const int64_t nt = ix->tile_off[t + 1] - ix->tile_off[t];
+          for (int64_t b = 0; b < nt; b += kWave) {
+            wtile.push_back(t);
+            wstart.push_back((int32_t)(pos + b));
+          }
+          pos += nt;
+          qend[t] = (int32_t)pos;
+        }
+        CHS_TRY(ix->own(&ix->wave_tile, wtile.size()));
+        CHS_TRY(ix->own(&ix->wave_start, wstart.size()));
+        CHS_TRY(ix->own(&ix->tile_qend, (size_t)T));
+        CHS_HIP(hipMemcpyAsync(ix->wave_tile, wtile.data(), 4 * wtile.size(), hipMemcpyHostToDevice, st));
+        CHS_HIP(hipMemcpyAsync(ix->wave_start, wstart.data(), 4 * wstart.size(), hipMemcpyHostToDevice, st));
+        CHS_HIP(hipMemcpyAsync(ix->tile_qend, qend.data(), 4 * (size_t)T, hipMemcpyHostToDevice, st));
+        CHS_HIP(hipStreamSynchronize(st));
+        ix->allq_waves = (int64_t)wtile.size();
+      } else {
+        ix->allq_waves = (ix->n + kWave - 1) / kWave;
+      }
       ix->allq = a;
-      (void)al;
     }
     plan->q = ix->allq;
+    plan->wave_tile = ix->wave_tile;
+    plan->wave_start = ix->wave_start;
+    plan->tile_qend = ix->tile_qend;
+    plan->nwaves = ix->allq_waves;
     return CHS_OK;
   }
   CHS_TRY(plan->q4.alloc(sizeof(float4) * qs->nq));
-  CHS_TRY(plan_impl(ix, qs->point_idx ? 1 : 2, qs->xyz, qs->point_idx, qs->nq,
+  const std::vector<int32_t> rank(1, 0);
+  CHS_TRY(plan_impl(ix, qs->point_idx ? 1 : 2, qs->xyz, qs->point_idx, qs->nq, rank,
                     plan->q4.as<float4>(), st));
   plan->q = plan->q4.as<float4>();
   return CHS_OK;
+}
+
+// ---------------------------------------------------------------- work items
+// A work item is one wave of at most 64 queries of one tile.
+struct Waves {
+  const float4* __restrict__ q4;  // processing order
+  int64_t nq;
+  int64_t nwaves;
+  const int32_t* __restrict__ wave_tile;   // NULL: one tile, waves of 64
+  const int32_t* __restrict__ wave_start;
+  const int32_t* __restrict__ tile_qend;
+  const Grid* __restrict__ tiles;
+  int32_t* counter;  // persistent launches: next work item
+};
+
+struct Item {
+  int tile;
+  int64_t t0, tend;
+};
+
+__device__ __forceinline__ Item item_of(const Waves& W, int64_t w) {
+  Item it;
+  if (W.wave_tile) {
+    // wave-uniform values: keep them in scalar registers
+    it.tile = uniform(W.wave_tile[w]);
+    it.t0 = uniform(W.wave_start[w]);
+    const int64_t e = uniform(W.tile_qend[it.tile]);
+    it.tend = it.t0 + kWave < e ? it.t0 + kWave : e;
+  } else {
+    it.tile = 0;
+    it.t0 = w * kWave;
+    it.tend = it.t0 + kWave < W.nq ? it.t0 + kWave : W.nq;
+  }
+  return it;
+}
+
+// Next work item of this wave: persistent waves take one from the counter
+// (a single lane performs the atomic), others own exactly one.
+__device__ __forceinline__ int64_t next_item(const Waves& W, int64_t* own, int lane) {
+  if (W.counter) {
+    int v = 0;
+    if (lane == 0) v = atomicAdd(W.counter, 1);
+    return (int64_t)uniform(__shfl(v, 0, kWave));
+  }
+  const int64_t w = *own;
+  *own = W.nwaves;  // the next request finds nothing left
+  return w;
+}
+
+__global__ void k_reset_counter(int32_t* c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
 }
 
 // ---------------------------------------------------------------- tile geometry
@@ -244,10 +381,9 @@ __device__ __forceinline__ bool column_near(const Grid& g, const Tile& t, int64_
 
 // ---------------------------------------------------------------- radius search
 struct RadiusArgs {
-  const float4* __restrict__ q4;
-  int64_t nq;
+  Waves W;
+  Grid g0;  // the grid of a single-tile index
   const float4* __restrict__ pts;
-  Grid g;
   Voxels vx;
   float r;
   int32_t* __restrict__ counts;         // count pass: [nq] caller order
@@ -288,35 +424,32 @@ __device__ __forceinline__ void flush_stage(const int32_t* seg_base, int lane, i
   nb = 0;
 }
 
-template <bool FILL>
-__global__ __launch_bounds__(kThreads) void k_radius(RadiusArgs A) {
-  __shared__ int32_t s_stage[FILL ? kWavesPerBlock * kWave * kStageStride : 1];
-  const int w = threadIdx.x / kWave, lane = lane_id();
-  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t t0 = ((int64_t)blk * kWavesPerBlock + w) * kWave;
-  if (t0 >= A.nq) return;
-  const int64_t t = t0 + lane;
-  const bool in = t < A.nq;
-  const float4 q = in ? A.q4[t] : make_float4(0.f, 0.f, 0.f, __uint_as_float(kInactive));
+template <bool FILL, bool MULTI, int FL>
+__device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it, int lane,
+                                            int32_t* seg_base) {
+  const Grid g = MULTI ? A.W.tiles[it.tile] : A.g0;
+  const int64_t t = it.t0 + lane;
+  const bool in = t < it.tend;
+  const float4 q = in ? A.W.q4[t] : make_float4(0.f, 0.f, 0.f, __uint_as_float(kInactive));
   const uint32_t wq = __float_as_uint(q.w);
-  const bool active = in && !(wq & kInactive) && (int64_t)(wq & ~kInactive) < A.nq;
   const uint32_t qid = wq & ~kInactive;
+  const bool active = in && !(wq & kInactive) && (int64_t)qid < A.W.nq;
   const Tile tb = tile_bounds(q, active);
   // fl32(r*r); lanes without a valid query get a negative bound so that no
   // candidate (D >= 0, or NaN) ever matches for them and they write nothing
   const float R = active ? A.r * A.r : -1.0f;
   const double pad = fmax((double)A.r * (1.0 + kPadRel), kPadAbs);
+  const int32_t poff = (int32_t)g.poff;
   int32_t cnt = 0;
   int64_t wpos = 0, wend = 0;
   int nb = 0;
-  int32_t* seg_base = s_stage + (FILL ? w * kWave * kStageStride : 0);
   int32_t* my_seg = seg_base + (FILL ? lane * kStageStride : 0);
   if (FILL && active) {
     wpos = A.offsets[qid];
     wend = A.offsets[qid + 1];
   }
   if (tb.any) {
-    const VBox bx = voxel_box(A.g, tb.lo, tb.hi, pad);
+    const VBox bx = voxel_box(g, tb.lo, tb.hi, pad);
     if (!bx.empty) {
       const int64_t nj = bx.hi[1] - bx.lo[1] + 1;
       const int64_t ncol = (bx.hi[0] - bx.lo[0] + 1) * nj;
@@ -325,7 +458,7 @@ __global__ __launch_bounds__(kThreads) void k_radius(RadiusArgs A) {
         int32_t b = 0, e = 0;
         if (c < ncol) {
           const int64_t ci = bx.lo[0] + c / nj, cj = bx.lo[1] + c % nj;
-          if (column_near(A.g, tb, ci, cj, pad)) column_run(A.vx, A.g, ci, cj, bx.lo[2], bx.hi[2], &b, &e);
+          if (column_near(g, tb, ci, cj, pad)) column_run<FL>(A.vx, g, ci, cj, bx.lo[2], bx.hi[2], &b, &e);
         }
         uint64_t m = __ballot(e > b);
         while (m) {
@@ -346,7 +479,7 @@ __global__ __launch_bounds__(kThreads) void k_radius(RadiusArgs A) {
               const float4 P = A.pts[p];
               const float dx = q.x - P.x, dy = q.y - P.y, dz = q.z - P.z;
               const float D = (dx * dx + dy * dy) + dz * dz;
-              if (D <= R) my_seg[nb++] = __float_as_int(P.w);
+              if (D <= R) my_seg[nb++] = __float_as_int(P.w) - poff;
               if (__ballot(nb == kStage)) flush_stage(seg_base, lane, nb, wpos, wend, A.nbr);
             }
           }
@@ -355,15 +488,33 @@ __global__ __launch_bounds__(kThreads) void k_radius(RadiusArgs A) {
     }
   }
   if (FILL) flush_stage(seg_base, lane, nb, wpos, wend, A.nbr);
-  if (!FILL && in && qid < A.nq) A.counts[qid] = active ? cnt : 0;
+  if (!FILL && in && (int64_t)qid < A.W.nq) A.counts[qid] = active ? cnt : 0;
+}
+
+// MULTI: per-item tile lookups and, if a counter is given, a persistent
+// loop over work items; otherwise one wave per item with tile 0's grid.
+template <bool FILL, bool MULTI, int FL>
+__global__ __launch_bounds__(kThreads) void k_radius(RadiusArgs A) {
+  __shared__ int32_t s_stage[FILL ? kWavesPerBlock * kWave * kStageStride : 1];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  int32_t* seg_base = s_stage + (FILL ? w * kWave * kStageStride : 0);
+  int64_t own = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
+  if (!MULTI) {
+    if (own < A.W.nwaves) radius_item<FILL, false, FL>(A, item_of(A.W, own), lane, seg_base);
+    return;
+  }
+  while (true) {
+    const int64_t item = next_item(A.W, &own, lane);
+    if (item >= A.W.nwaves) break;
+    radius_item<FILL, true, FL>(A, item_of(A.W, item), lane, seg_base);
+  }
 }
 
 // ---------------------------------------------------------------- k-NN
 struct KnnArgs {
-  const float4* __restrict__ q4;
-  int64_t nq;
+  Waves W;
+  Grid g0;  // the grid of a single-tile index
   const float4* __restrict__ pts;
-  Grid g;
   Voxels vx;
   int32_t k;
   float rmax2;  // fl32(r_max^2), +inf without a radius cap
@@ -398,24 +549,20 @@ __device__ __forceinline__ void scan_run(const float4* __restrict__ pts, int32_t
   }
 }
 
-template <int KC>
-__global__ __launch_bounds__(kThreads) void k_knn(KnnArgs A) {
-  const int w = threadIdx.x / kWave, lane = lane_id();
-  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t t0 = ((int64_t)blk * kWavesPerBlock + w) * kWave;
-  if (t0 >= A.nq) return;
-  const int64_t t = t0 + lane;
-  const bool in = t < A.nq;
-  const float4 q = in ? A.q4[t] : make_float4(0.f, 0.f, 0.f, __uint_as_float(kInactive));
+template <int KC, bool MULTI, int FL>
+__device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int lane) {
+  const Grid g = MULTI ? A.W.tiles[it.tile] : A.g0;
+  const int64_t t = it.t0 + lane;
+  const bool in = t < it.tend;
+  const float4 q = in ? A.W.q4[t] : make_float4(0.f, 0.f, 0.f, __uint_as_float(kInactive));
   const uint32_t wq = __float_as_uint(q.w);
-  const bool active = in && !(wq & kInactive);
   const uint32_t qid = wq & ~kInactive;
+  const bool active = in && !(wq & kInactive) && (int64_t)qid < A.W.nq;
   const Tile tb = tile_bounds(q, active);
   uint64_t best[KC];
 #pragma unroll
   for (int i = 0; i < KC; ++i) best[i] = ~0ull;
   if (tb.any) {
-    const Grid& g = A.g;
     // ring 0: the voxels holding the tile's queries (clamped into the grid)
     VBox B;
     B.empty = false;
@@ -443,10 +590,10 @@ __global__ __launch_bounds__(kThreads) void k_knn(KnnArgs A) {
           const bool inner = !V.empty && ci >= V.lo[0] && ci <= V.hi[0] && cj >= V.lo[1] &&
                              cj <= V.hi[1];
           if (!inner) {
-            column_run(A.vx, g, ci, cj, B.lo[2], B.hi[2], &b0, &e0);
+            column_run<FL>(A.vx, g, ci, cj, B.lo[2], B.hi[2], &b0, &e0);
           } else {
-            if (B.lo[2] < V.lo[2]) column_run(A.vx, g, ci, cj, B.lo[2], V.lo[2] - 1, &b0, &e0);
-            if (B.hi[2] > V.hi[2]) column_run(A.vx, g, ci, cj, V.hi[2] + 1, B.hi[2], &b1, &e1);
+            if (B.lo[2] < V.lo[2]) column_run<FL>(A.vx, g, ci, cj, B.lo[2], V.lo[2] - 1, &b0, &e0);
+            if (B.hi[2] > V.hi[2]) column_run<FL>(A.vx, g, ci, cj, V.hi[2] + 1, B.hi[2], &b1, &e1);
           }
         }
         uint64_t m0 = __ballot(e0 > b0);
@@ -506,22 +653,110 @@ __global__ __launch_bounds__(kThreads) void k_knn(KnnArgs A) {
       }
     }
   }
-  if (in) {
+  if (in && (int64_t)qid < A.W.nq) {
     int32_t* ro = A.idx + (int64_t)qid * A.k;
     float* rd = A.d2 + (int64_t)qid * A.k;
+    const int32_t poff = (int32_t)g.poff;
 #pragma unroll
     for (int i = 0; i < KC; ++i) {
       if (i < A.k) {
         const uint64_t key = active ? best[i] : ~0ull;
         const bool ok = key != ~0ull;
-        ro[i] = ok ? (int32_t)(uint32_t)key : -1;
+        ro[i] = ok ? (int32_t)(uint32_t)key - poff : -1;
         rd[i] = ok ? __uint_as_float((uint32_t)(key >> 32)) : INFINITY;
       }
     }
   }
 }
 
+template <int KC, bool MULTI, int FL>
+__global__ __launch_bounds__(kThreads) void k_knn(KnnArgs A) {
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  int64_t own = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
+  if (!MULTI) {
+    if (own < A.W.nwaves) knn_item<KC, false, FL>(A, item_of(A.W, own), lane);
+    return;
+  }
+  while (true) {
+    const int64_t item = next_item(A.W, &own, lane);
+    if (item >= A.W.nwaves) break;
+    knn_item<KC, true, FL>(A, item_of(A.W, item), lane);
+  }
+}
+
 // ---------------------------------------------------------------- host side
+// Launch geometry: one wave per work item, or for persistent launches one
+// block per 4 waves up to 32 waves per CU of a 256-CU part.
+static Waves make_waves(chs_index ix, const QueryPlan& plan, int32_t* counter) {
+  Waves W;
+  W.q4 = plan.q;
+  W.nq = plan.nq;
+  W.nwaves = plan.nwaves;
+  W.wave_tile = plan.wave_tile;
+  W.wave_start = plan.wave_start;
+  W.tile_qend = plan.tile_qend;
+  W.tiles = ix->tiles_d;
+  W.counter = counter;
+  return W;
+}
+
+// per-item tile lookups and persistent waves are needed by batched indexes
+// and by the persistent option; a plain index uses the lighter kernels
+static bool multi(chs_index ix) { return ix->ntiles > 1 || ix->persistent; }
+
+static chs_status launch_dims(chs_index ix, const QueryPlan& plan, hipStream_t st,
+                              int32_t** counter, unsigned* nblocks) {
+  const int64_t nb = (plan.nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
+  *counter = nullptr;
+  *nblocks = (unsigned)(nb > 0 ? nb : 1);
+  if (ix->persistent) {
+    if (!ix->work_counter) CHS_TRY(ix->own(&ix->work_counter, 1));
+    k_reset_counter<<<1, kWave, 0, st>>>(ix->work_counter);
+    CHS_LAUNCH_CHECK();
+    *counter = ix->work_counter;
+    const int64_t cap = 256 * 8;
+    *nblocks = (unsigned)(nb < cap ? (nb > 0 ? nb : 1) : cap);
+  }
+  return CHS_OK;
+}
+
+// kernel instance for the index's flavor and launch mode
+template <bool FILL>
+static void launch_radius(chs_index ix, unsigned nb, hipStream_t st, const RadiusArgs& A) {
+  const bool mt = multi(ix);
+  switch (ix->flavor) {
+    case CHS_DENSE:
+      mt ? k_radius<FILL, true, CHS_DENSE><<<nb, kThreads, 0, st>>>(A)
+         : k_radius<FILL, false, CHS_DENSE><<<nb, kThreads, 0, st>>>(A);
+      break;
+    case CHS_SPARSE:
+      mt ? k_radius<FILL, true, CHS_SPARSE><<<nb, kThreads, 0, st>>>(A)
+         : k_radius<FILL, false, CHS_SPARSE><<<nb, kThreads, 0, st>>>(A);
+      break;
+    default:
+      mt ? k_radius<FILL, true, CHS_MIXED><<<nb, kThreads, 0, st>>>(A)
+         : k_radius<FILL, false, CHS_MIXED><<<nb, kThreads, 0, st>>>(A);
+  }
+}
+
+template <int KC>
+static void launch_knn(chs_index ix, unsigned nb, hipStream_t st, const KnnArgs& A) {
+  const bool mt = multi(ix);
+  switch (ix->flavor) {
+    case CHS_DENSE:
+      mt ? k_knn<KC, true, CHS_DENSE><<<nb, kThreads, 0, st>>>(A)
+         : k_knn<KC, false, CHS_DENSE><<<nb, kThreads, 0, st>>>(A);
+      break;
+    case CHS_SPARSE:
+      mt ? k_knn<KC, true, CHS_SPARSE><<<nb, kThreads, 0, st>>>(A)
+         : k_knn<KC, false, CHS_SPARSE><<<nb, kThreads, 0, st>>>(A);
+      break;
+    default:
+      mt ? k_knn<KC, true, CHS_MIXED><<<nb, kThreads, 0, st>>>(A)
+         : k_knn<KC, false, CHS_MIXED><<<nb, kThreads, 0, st>>>(A);
+  }
+}
+
 static chs_status radius_count_impl(chs_index ix, const QueryPlan& plan, float r, int64_t* offsets,
                                     hipStream_t st) {
   Alloc al = ix->al;
@@ -530,9 +765,12 @@ static chs_status radius_count_impl(chs_index ix, const QueryPlan& plan, float r
   Buf counts(&al);
   CHS_TRY(counts.alloc(sizeof(int32_t) * (nq > 0 ? nq : 1)));
   if (nq > 0) {
-    RadiusArgs A{plan.q, nq, ix->pts, ix->grid(), ix->voxels(), r, counts.as<int32_t>(), nullptr,
-                 nullptr};
-    k_radius<false><<<grid_for(nq), kThreads, 0, st>>>(A);
+    int32_t* ctr;
+    unsigned nb;
+    CHS_TRY(launch_dims(ix, plan, st, &ctr, &nb));
+    RadiusArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), r,
+                 counts.as<int32_t>(), nullptr, nullptr};
+    launch_radius<false>(ix, nb, st, A);
     CHS_LAUNCH_CHECK();
   }
   CHS_TRY(exclusive_scan_i32_i64(al, counts.as<int32_t>(), offsets, nq));
@@ -541,10 +779,13 @@ static chs_status radius_count_impl(chs_index ix, const QueryPlan& plan, float r
 
 static chs_status radius_fill_impl(chs_index ix, const QueryPlan& plan, float r,
                                    const int64_t* offsets, int32_t* nbr, hipStream_t st) {
-  const int64_t nq = plan.nq;
-  if (nq == 0) return CHS_OK;
-  RadiusArgs A{plan.q, nq, ix->pts, ix->grid(), ix->voxels(), r, nullptr, offsets, nbr};
-  k_radius<true><<<grid_for(nq), kThreads, 0, st>>>(A);
+  if (plan.nq == 0) return CHS_OK;
+  int32_t* ctr;
+  unsigned nb;
+  CHS_TRY(launch_dims(ix, plan, st, &ctr, &nb));
+  RadiusArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), r, nullptr,
+               offsets, nbr};
+  launch_radius<true>(ix, nb, st, A);
   CHS_LAUNCH_CHECK();
   return CHS_OK;
 }
@@ -667,16 +908,18 @@ extern "C" chs_status chs_knn(chs_index ix, const chs_queries* qs, int32_t k, fl
   QueryPlan plan(&al);
   CHS_TRY(plan_queries(ix, qs, &plan, st));
   const float rmax2 = std::isinf(r_max) ? INFINITY : r_max * r_max;
-  KnnArgs A{plan.q, plan.nq, ix->pts, ix->grid(), ix->voxels(), k, rmax2, idx, d2};
-  const unsigned nb = grid_for(plan.nq);
+  int32_t* ctr;
+  unsigned nb;
+  CHS_TRY(launch_dims(ix, plan, st, &ctr, &nb));
+  KnnArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), k, rmax2, idx, d2};
   if (k <= 8)
-    k_knn<8><<<nb, kThreads, 0, st>>>(A);
+    launch_knn<8>(ix, nb, st, A);
   else if (k <= 16)
-    k_knn<16><<<nb, kThreads, 0, st>>>(A);
+    launch_knn<16>(ix, nb, st, A);
   else if (k <= 32)
-    k_knn<32><<<nb, kThreads, 0, st>>>(A);
+    launch_knn<32>(ix, nb, st, A);
   else
-    k_knn<64><<<nb, kThreads, 0, st>>>(A);
+    launch_knn<64>(ix, nb, st, A);
   CHS_LAUNCH_CHECK();
   return CHS_OK;
 }

@@ -70,14 +70,25 @@ def _queries(queries, n):
     raise ValueError("queries: int32 [nq] point indices or float64 [nq,3] coordinates")
 
 
+def _params(cell, dims, flavor, mixed_dense_pct, max_dense_cells):
+    c = [float(cell)] * 3 if not hasattr(cell, "__len__") else [float(v) for v in cell]
+    return BuildParams(_lib.FLAVORS[flavor], dims, (ctypes.c_double * 3)(*c), mixed_dense_pct, 0,
+                       max_dense_cells)
+
+
 class GridIndex:
     """Cheesemap grid index over a cloud ``xyz`` (float64 [n,3] on the GPU).
 
     flavor: "dense" | "sparse" | "mixed" (Section 3.3); dims: 3 or 2;
-    cell: voxel edge in metres (scalar or per axis)."""
+    cell: voxel edge in metres (scalar or per axis).
+
+    With ``tile_off`` (host sequence of ntiles+1 point offsets) the index is
+    a batch of independent tiles stored back to back in ``xyz``; ``cell``
+    may then be one value per tile.  Searches on a batched index take every
+    point as a query (of its own tile) and return tile-local indices."""
 
     def __init__(self, xyz, cell=1.0, dims=3, flavor="dense", mixed_dense_pct=80,
-                 max_dense_cells=0, stream=None):
+                 max_dense_cells=0, stream=None, tile_off=None):
         if not (isinstance(xyz, torch.Tensor) and xyz.is_cuda and xyz.dtype == torch.float64):
             raise ValueError("xyz must be a float64 CUDA tensor [n,3]")
         if xyz.dim() != 2 or xyz.shape[1] != 3:
@@ -85,19 +96,44 @@ class GridIndex:
         self.device = xyz.device
         self._alloc = TorchAllocator(self.device)
         xyz = xyz.contiguous()
-        c = [float(cell)] * 3 if not hasattr(cell, "__len__") else [float(v) for v in cell]
-        p = BuildParams(_lib.FLAVORS[flavor], dims, (ctypes.c_double * 3)(*c), mixed_dense_pct, 0,
-                        max_dense_cells)
         h = ctypes.c_void_p()
         self._h = None
+        self.ntiles = 1
         with torch.cuda.device(self.device):
-            st = lib().chs_build(xyz.data_ptr(), xyz.shape[0], ctypes.byref(p),
-                                 ctypes.byref(self._alloc.struct), _stream(stream), ctypes.byref(h))
-        check(st, "chs_build")
+            if tile_off is None:
+                p = _params(cell, dims, flavor, mixed_dense_pct, max_dense_cells)
+                st = lib().chs_build(xyz.data_ptr(), xyz.shape[0], ctypes.byref(p),
+                                     ctypes.byref(self._alloc.struct), _stream(stream),
+                                     ctypes.byref(h))
+                check(st, "chs_build")
+            else:
+                toff = [int(v) for v in tile_off]
+                T = len(toff) - 1
+                cells = list(cell) if (hasattr(cell, "__len__") and len(cell) == T) else [cell] * T
+                arr = (BuildParams * T)(*[_params(c, dims, flavor, mixed_dense_pct,
+                                                  max_dense_cells) for c in cells])
+                toff_c = (ctypes.c_int64 * (T + 1))(*toff)
+                st = lib().chs_build_batch(xyz.data_ptr(), xyz.shape[0], toff_c, T, arr,
+                                           ctypes.byref(self._alloc.struct), _stream(stream),
+                                           ctypes.byref(h))
+                check(st, "chs_build_batch")
+                self.ntiles = T
+                self.tile_off = toff
         self._h = h
         self.n = xyz.shape[0]
         self.flavor = flavor
         self.dims = dims
+
+    def set_persistent(self, on=True):
+        """Persistent searches: one wave per hardware slot pulling 64-query
+        work items from a device counter (default for batched indexes)."""
+        check(lib().chs_index_set_option(self._h, 1, 1 if on else 0), "chs_index_set_option")
+
+    def tile_info(self, t):
+        inf = IndexInfo()
+        check(lib().chs_tile_info(self._h, t, ctypes.byref(inf)), "chs_tile_info")
+        return dict(origin=list(inf.origin), max32=list(inf.max32), cell=list(inf.cell),
+                    ncell=list(inf.ncell), n_points=inf.n_points, dims=inf.dims)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -117,7 +153,7 @@ class GridIndex:
         return dict(origin=list(inf.origin), max32=list(inf.max32), cell=list(inf.cell),
                     ncell=list(inf.ncell), n_points=inf.n_points, n_nonempty=inf.n_nonempty,
                     n_dense_slices=inf.n_dense_slices, device_bytes=inf.device_bytes,
-                    flavor=inf.flavor, dims=inf.dims)
+                    flavor=inf.flavor, dims=inf.dims, ntiles=inf.ntiles)
 
     def arrays(self):
         """Copies of the index's device arrays (for inspection and tests)."""
@@ -168,6 +204,19 @@ class GridIndex:
         return off, nbr
 
     # ---- k-NN (Section 3.4.2)
+    def knn_into(self, k, idx, d2, queries=None, r_max=math.inf, stream=None):
+        """k-NN into preallocated idx [nq,k] int32 and d2 [nq,k] float32
+        (no allocation: usable inside a captured graph)."""
+        q, nq, keep = _queries(queries, self.n)
+        if idx.shape != (nq, k) or d2.shape != (nq, k) or idx.dtype != torch.int32 \
+                or d2.dtype != torch.float32 or not (idx.is_contiguous() and d2.is_contiguous()):
+            raise ValueError("idx / d2 must be contiguous [nq,k] int32 / float32")
+        with torch.cuda.device(self.device):
+            check(lib().chs_knn(self._h, ctypes.byref(q), k, ctypes.c_float(r_max),
+                                idx.data_ptr() if nq else None, d2.data_ptr() if nq else None,
+                                _stream(stream)), "chs_knn")
+        return idx, d2
+
     def knn(self, k, queries=None, r_max=math.inf, stream=None):
         """(idx int32 [nq,k], d2 float32 [nq,k]) sorted by (d2, index);
         missing entries are (-1, +inf)."""

@@ -1,0 +1,146 @@
+"""GPU parity of batched indexes: many uneven tiles built and searched in one
+go (persistent waves pulling work items), checked tile by tile against the
+CPU oracle, against per-tile indexes, across launch modes, and when the
+searches are captured in a hipGraph and replayed."""
+import numpy as np
+import pytest
+
+import cloudgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _tiles(ntiles=24, seed=3, lo=300, hi=40_000):
+    """Uneven ALS-like tiles: sizes log-uniform, densities 2-20 points per
+    square metre (the batched workload's recipe at a smaller scale)."""
+    nt, dens, tile_cloud = cloudgen.config3_tiles(seed=seed, ntiles=ntiles, total=ntiles * 6000,
+                                                  lo=lo, hi=hi)
+    tiles = [tile_cloud(t) for t in range(ntiles)]
+    return tiles, dens
+
+
+def _batch(tiles, cells, flavor, dev):
+    from paper_2502_11602_amd import GridIndex
+    xyz = np.concatenate(tiles)
+    toff = np.concatenate([[0], np.cumsum([len(t) for t in tiles])])
+    ix = GridIndex(torch.from_numpy(xyz).to(dev), cell=list(cells), flavor=flavor,
+                   tile_off=toff.tolist())
+    return ix, toff
+
+
+def _csr_sorted(off, nbr):
+    rows = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    o = np.lexsort((nbr, rows))
+    return rows[o], nbr[o]
+
+
+@pytest.mark.parametrize("flavor", ["dense", "sparse"])
+def test_batch_matches_oracle_per_tile(flavor):
+    dev = _dev()
+    tiles, dens = _tiles()
+    r, k = 1.0, 16
+    # per-tile voxel edge: about one voxel per r at high density, larger when sparse
+    cells = [float(np.clip(r * np.sqrt(8.0 / d), 0.5 * r, 2.0 * r)) for d in dens]
+    ix, toff = _batch(tiles, cells, flavor, dev)
+    assert ix.info()["ntiles"] == len(tiles)
+    off, nbr = ix.radius(r)
+    idx, d2 = ix.knn(k)
+    off = off.cpu().numpy(); nbr = nbr.cpu().numpy()
+    idx = idx.cpu().numpy(); d2 = d2.cpu().numpy()
+    for t, tile in enumerate(tiles):
+        ox = oracle.OracleIndex(tile, cells[t], flavor=flavor)
+        inf = ix.tile_info(t)
+        assert inf["origin"] == ox.origin.tolist() and inf["ncell"] == ox.ncell.tolist()
+        oo, on = ox.radius(r, nthreads=8)
+        a, b = toff[t], toff[t + 1]
+        o2 = off[a:b + 1] - off[a]
+        np.testing.assert_array_equal(o2, oo)
+        g = _csr_sorted(o2, nbr[off[a]:off[b]])
+        w = _csr_sorted(oo, on)
+        np.testing.assert_array_equal(g[0], w[0])
+        np.testing.assert_array_equal(g[1], w[1])
+        oi, od = ox.knn(k, nthreads=8)
+        np.testing.assert_array_equal(idx[a:b], oi)
+        np.testing.assert_array_equal(d2[a:b], od)
+
+
+def test_batch_launch_modes_and_per_tile_indexes_agree():
+    from paper_2502_11602_amd import GridIndex
+    dev = _dev()
+    tiles, dens = _tiles(ntiles=16, seed=5)
+    cells = [1.0] * len(tiles)
+    ix, toff = _batch(tiles, cells, "dense", dev)
+    o1, n1 = ix.radius(1.5)
+    i1, d1 = ix.knn(12)
+    ix.set_persistent(False)
+    o2, n2 = ix.radius(1.5)
+    i2, d2 = ix.knn(12)
+    assert torch.equal(o1, o2) and torch.equal(n1, n2)
+    assert torch.equal(i1, i2) and torch.equal(d1, d2)
+    # one index per tile gives the same rows (as sets) and the same k-NN
+    for t, tile in enumerate(tiles):
+        one = GridIndex(torch.from_numpy(tile).to(dev), cell=cells[t])
+        oo, on = one.radius(1.5)
+        a, b = toff[t], toff[t + 1]
+        seg = o1[a:b + 1] - o1[a]
+        assert torch.equal(seg, oo)
+        g = _csr_sorted(seg.cpu().numpy(), n1[int(o1[a]):int(o1[b])].cpu().numpy())
+        w = _csr_sorted(oo.cpu().numpy(), on.cpu().numpy())
+        np.testing.assert_array_equal(g[1], w[1])
+        ii, dd = one.knn(12)
+        assert torch.equal(i1[a:b], ii) and torch.equal(d1[a:b], dd)
+
+
+def test_batch_search_in_hip_graph():
+    """Fill and k-NN captured once, replayed several times with eager work in
+    between; every replay equals the eager results."""
+    dev = _dev()
+    tiles, dens = _tiles(ntiles=20, seed=8)
+    ix, toff = _batch(tiles, [1.0] * len(tiles), "sparse", dev)
+    r, k = 1.0, 16
+    off, total = ix.radius_count(r)
+    nbr_eager = ix.radius_fill(r, off, total)
+    idx_eager, d2_eager = ix.knn(k)
+    torch.cuda.synchronize()
+    nbr = torch.empty_like(nbr_eager)
+    idx = torch.empty_like(idx_eager)
+    d2 = torch.empty_like(d2_eager)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        # warm up on the capture stream
+        ix.radius_fill(r, off, total, out=nbr)
+        ix.knn_into(k, idx, d2)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ix.radius_fill(r, off, total, out=nbr)
+        ix.knn_into(k, idx, d2)
+    for rep in range(3):
+        nbr.fill_(-7)
+        idx.fill_(-7)
+        d2.fill_(-7.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(nbr, nbr_eager), rep
+        assert torch.equal(idx, idx_eager), rep
+        assert torch.equal(d2, d2_eager), rep
+
+
+def test_batch_rejects_point_queries():
+    from paper_2502_11602_amd import ChsError
+    dev = _dev()
+    tiles, _ = _tiles(ntiles=3, seed=9, hi=3000)
+    ix, _ = _batch(tiles, [1.0] * 3, "dense", dev)
+    with pytest.raises(ChsError):
+        ix.knn(4, torch.tensor([0, 1], dtype=torch.int32, device=dev))
