@@ -144,3 +144,21 @@ def test_batch_rejects_point_queries():
     ix, _ = _batch(tiles, [1.0] * 3, "dense", dev)
     with pytest.raises(ChsError):
         ix.knn(4, torch.tensor([0, 1], dtype=torch.int32, device=dev))
+
+
+def test_autotuner_picks_a_timed_candidate_and_caches(tmp_path):
+    from paper_2502_11602_amd.autotune import Autotuner
+    dev = _dev()
+    tiles, _ = _tiles(ntiles=3, seed=11, lo=2000, hi=20000)
+    ts = [torch.from_numpy(t).to(dev) for t in tiles]
+    tu = Autotuner(cache_path=str(tmp_path / "tune.json"), repeats=1)
+    cells, flavor = tu.choose(ts, 1.0, 16)
+    assert len(cells) == 3 and flavor in ("dense", "sparse")
+    tried = {(t["key"], t["cell"]) for t in tu.trials}
+    for t, c in zip(ts, cells):
+        from paper_2502_11602_amd.autotune import tile_stats
+        n, _, d, _ = tile_stats(t)
+        assert (tu.key(n, d, 1.0, 16), c) in tried
+    tu.save()
+    again = Autotuner(cache_path=str(tmp_path / "tune.json"), repeats=1)
+    assert again.choose(ts, 1.0, 16)[0] == cells and not again.trials
