@@ -312,6 +312,18 @@ __device__ __forceinline__ void column_run(const Voxels& vx, const Grid& g, int6
   }
 }
 
+// The stored points seen through the constant address space: the index
+// never changes during a search, and loads from this space at wave-uniform
+// addresses are issued by the scalar unit even in kernels that also store
+// (where the compiler cannot prove a global pointer read-only).
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef const f4v __attribute__((address_space(4)))* const_pts;
+__device__ __forceinline__ const_pts as_const(const float4* p) { return (const_pts)p; }
+__device__ __forceinline__ float4 load_const(const_pts p, int32_t i) {
+  const f4v v = p[i];
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // Block index remapped so that consecutive logical blocks run on the same
 // XCD (the hardware deals blocks round-robin over the 8 XCDs, each with its
 // own L2): spatially adjacent query tiles then share an L2.

@@ -399,6 +399,7 @@ struct RadiusArgs {
 // partial lines.  Every store is also checked against its row's end.
 constexpr int kStage = 32;                 // entries per lane
 constexpr int kStageStride = kStage + 1;   // padded against LDS bank conflicts
+constexpr int kGroup = 4;                   // candidates loaded together in the fill
 
 __device__ __forceinline__ void flush_stage(const int32_t* seg_base, int lane, int& nb,
                                             int64_t& wpos, int64_t wend,
@@ -475,12 +476,29 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
               cnt += D <= R ? 1 : 0;
             }
           } else {
-            for (int32_t p = rb; p < re; ++p) {
-              const float4 P = A.pts[p];
+            // groups of kGroup candidates: their loads are issued together,
+            // and the stage is flushed whenever a lane could overflow it in
+            // the next group
+            const_pts cp = as_const(A.pts);
+            int32_t p = rb;
+            for (; p + kGroup <= re; p += kGroup) {
+              float4 P[kGroup];
+#pragma unroll
+              for (int u = 0; u < kGroup; ++u) P[u] = load_const(cp, p + u);
+#pragma unroll
+              for (int u = 0; u < kGroup; ++u) {
+                const float dx = q.x - P[u].x, dy = q.y - P[u].y, dz = q.z - P[u].z;
+                const float D = (dx * dx + dy * dy) + dz * dz;
+                if (D <= R) my_seg[nb++] = __float_as_int(P[u].w) - poff;
+              }
+              if (__ballot(nb > kStage - kGroup)) flush_stage(seg_base, lane, nb, wpos, wend, A.nbr);
+            }
+            for (; p < re; ++p) {
+              const float4 P = load_const(cp, p);
               const float dx = q.x - P.x, dy = q.y - P.y, dz = q.z - P.z;
               const float D = (dx * dx + dy * dy) + dz * dz;
               if (D <= R) my_seg[nb++] = __float_as_int(P.w) - poff;
-              if (__ballot(nb == kStage)) flush_stage(seg_base, lane, nb, wpos, wend, A.nbr);
+              if (__ballot(nb > kStage - kGroup)) flush_stage(seg_base, lane, nb, wpos, wend, A.nbr);
             }
           }
         }
