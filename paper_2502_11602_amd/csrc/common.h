@@ -189,6 +189,24 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
+// Broadcast of lane 0's value.  Applied to a value every lane already holds,
+// it tells the compiler that the value is wave-uniform, so it lives in
+// scalar registers and the loops it bounds are not divergent.
+__device__ __forceinline__ int32_t first_lane(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float first_lane(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ int64_t first_lane(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double first_lane(double v) {
+  return __longlong_as_double(first_lane((int64_t)__double_as_longlong(v)));
+}
+
+// Reductions over the full wave (every lane active); the result is uniform.
 template <class T>
 __device__ __forceinline__ T wave_min(T v) {
 #pragma unroll
@@ -196,7 +214,7 @@ __device__ __forceinline__ T wave_min(T v) {
     T o = __shfl_xor(v, m, kWave);
     v = o < v ? o : v;
   }
-  return v;
+  return first_lane(v);
 }
 
 template <class T>
@@ -206,7 +224,7 @@ __device__ __forceinline__ T wave_max(T v) {
     T o = __shfl_xor(v, m, kWave);
     v = o > v ? o : v;
   }
-  return v;
+  return first_lane(v);
 }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }

@@ -338,6 +338,9 @@ struct VBox {
   int64_t lo[3], hi[3];
   bool empty;
 };
+struct IBox {
+  int32_t lo[3], hi[3];
+};
 
 // Voxel box covering [lo - pad, hi + pad] along every indexed axis, clamped
 // to the grid; empty when it misses the grid.
@@ -353,14 +356,17 @@ __device__ __forceinline__ VBox voxel_box(const Grid& g, const float* lo, const 
     }
     const double clo = floor(((double)lo[a] - pad) / g.s[a]);
     const double chi = floor(((double)hi[a] + pad) / g.s[a]);
-    if (chi < 0.0 || clo > (double)(g.n[a] - 1)) {
+    // uniform values computed on the vector unit (there is no scalar FP64)
+    // are moved back to scalar registers, so the loops they bound are not
+    // divergent
+    if (first_lane((int32_t)(chi < 0.0 || clo > (double)(g.n[a] - 1)))) {
       b.empty = true;
       b.lo[a] = 0;
       b.hi[a] = -1;
       continue;
     }
-    b.lo[a] = clo < 0.0 ? 0 : (int64_t)clo;
-    b.hi[a] = chi > (double)(g.n[a] - 1) ? g.n[a] - 1 : (int64_t)chi;
+    b.lo[a] = first_lane(clo < 0.0 ? (int64_t)0 : (int64_t)clo);
+    b.hi[a] = first_lane(chi > (double)(g.n[a] - 1) ? g.n[a] - 1 : (int64_t)chi);
   }
   return b;
 }
@@ -478,7 +484,10 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
           } else {
             // groups of kGroup candidates: their loads are issued together,
             // and the stage is flushed whenever a lane could overflow it in
-            // the next group
+            // the next group.  Every candidate is written to the next free
+            // slot and kept only if it matches (no divergent branch per
+            // candidate); a stage never holds more than kStage - kGroup
+            // entries before a group, so the slot is always in range.
             const_pts cp = as_const(A.pts);
             int32_t p = rb;
             for (; p + kGroup <= re; p += kGroup) {
@@ -489,7 +498,8 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
               for (int u = 0; u < kGroup; ++u) {
                 const float dx = q.x - P[u].x, dy = q.y - P[u].y, dz = q.z - P[u].z;
                 const float D = (dx * dx + dy * dy) + dz * dz;
-                if (D <= R) my_seg[nb++] = __float_as_int(P[u].w) - poff;
+                my_seg[nb] = __float_as_int(P[u].w) - poff;
+                nb += D <= R ? 1 : 0;
               }
               if (__ballot(nb > kStage - kGroup)) flush_stage(seg_base, lane, nb, wpos, wend, A.nbr);
             }
@@ -497,7 +507,8 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
               const float4 P = load_const(cp, p);
               const float dx = q.x - P.x, dy = q.y - P.y, dz = q.z - P.z;
               const float D = (dx * dx + dy * dy) + dz * dz;
-              if (D <= R) my_seg[nb++] = __float_as_int(P.w) - poff;
+              my_seg[nb] = __float_as_int(P.w) - poff;
+              nb += D <= R ? 1 : 0;
               if (__ballot(nb > kStage - kGroup)) flush_stage(seg_base, lane, nb, wpos, wend, A.nbr);
             }
           }
@@ -540,8 +551,26 @@ struct KnnArgs {
   float* __restrict__ d2;
 };
 
-// Sorted insertion of key x into best[0..KC) (ascending), dropping the last:
-// best'[i] = max(best[i-1], min(x, best[i])).
+// The list of a lane is kept sorted in registers, best[0..KC) ascending, as
+// 64-bit keys (distance bits << 32 | original index).  Candidates below the
+// current k-th key are appended to a per-lane buffer in LDS; when some lane's
+// buffer could overflow, and at the end of every ring, each lane sorts its
+// buffer and merges it in with a bitonic network, so the wave pays for one
+// merge per KB accepted candidates of its busiest lane instead of one
+// insertion for every candidate that any lane accepts.
+// Lists shorter than kKnnBufMin take the insertion directly: their
+// insertion network is short enough that buffering does not pay.
+constexpr int kKnnBufMin = 16;
+constexpr int kKnnBufCap = 16;
+template <int KC>
+struct KnnBuf {
+  static constexpr bool on = KC >= kKnnBufMin;
+  static constexpr int KB = KC < kKnnBufCap ? KC : kKnnBufCap;  // buffered keys per lane
+  static constexpr int stride = KB + 1;  // odd, against bank conflicts
+};
+
+// Sorted insertion of key x < best[KC-1] into best[0..KC) (ascending),
+// dropping the last entry: best'[i] = max(best[i-1], min(x, best[i])).
 template <int KC>
 __device__ __forceinline__ void topk_insert(uint64_t (&best)[KC], uint64_t x) {
 #pragma unroll
@@ -552,23 +581,121 @@ __device__ __forceinline__ void topk_insert(uint64_t (&best)[KC], uint64_t x) {
   best[0] = x < best[0] ? x : best[0];
 }
 
+__device__ __forceinline__ void cmp_swap(uint64_t& a, uint64_t& b) {
+  const bool s = b < a;
+  const uint64_t lo = s ? b : a, hi = s ? a : b;
+  a = lo;
+  b = hi;
+}
+
+template <int N>
+__device__ __forceinline__ void bitonic_sort(uint64_t (&x)[N]) {
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int l = i ^ j;
+        if (l > i) {
+          if ((i & k) == 0) cmp_swap(x[i], x[l]);
+          else cmp_swap(x[l], x[i]);
+        }
+      }
+}
+
+// x bitonic -> x ascending
+template <int N>
+__device__ __forceinline__ void bitonic_merge(uint64_t (&x)[N]) {
+#pragma unroll
+  for (int j = N >> 1; j > 0; j >>= 1)
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const int l = i ^ j;
+      if (l > i) cmp_swap(x[i], x[l]);
+    }
+}
+
+// best[k-1] for the uniform k
+// (masks rather than selects, which the compiler would otherwise turn into
+// an indexed load from a memory copy of the list)
 template <int KC>
-__device__ __forceinline__ void scan_run(const float4* __restrict__ pts, int32_t rb, int32_t re,
-                                         float4 q, float rmax2, uint64_t (&best)[KC]) {
-#pragma unroll 2
-  for (int32_t p = rb; p < re; ++p) {
-    const float4 P = pts[p];
+__device__ __forceinline__ uint64_t kth_key(const uint64_t (&best)[KC], int k) {
+  uint64_t v = 0;
+#pragma unroll
+  for (int i = 0; i < KC; ++i) v |= best[i] & (0ull - (uint64_t)(i == k - 1));
+  return v;
+}
+
+// Merge the lane's nb buffered keys into best: the buffer sorted ascending,
+// min(best[KC-1-j], buf[j]) forms a bitonic sequence holding the KC smallest
+// keys of both, which the merge network sorts.
+template <int KC>
+__device__ __forceinline__ void merge_buffer(uint64_t (&best)[KC], const uint64_t* seg, int& nb) {
+  constexpr int KB = KnnBuf<KC>::KB;
+  uint64_t b[KB];
+#pragma unroll
+  for (int i = 0; i < KB; ++i) b[i] = i < nb ? seg[i] : ~0ull;
+  bitonic_sort<KB>(b);
+#pragma unroll
+  for (int j = 0; j < KB; ++j) best[KC - 1 - j] = b[j] < best[KC - 1 - j] ? b[j] : best[KC - 1 - j];
+  bitonic_merge<KC>(best);
+  nb = 0;
+}
+
+// Scan the candidates [rb, re) of one run (wave-uniform), groups of kGroup
+// loaded together through the scalar unit.
+template <int KC>
+__device__ __forceinline__ void knn_scan(const_pts cp, int32_t rb, int32_t re, float4 q,
+                                         float rmax2, int k, uint64_t (&best)[KC], uint64_t& kthk,
+                                         uint64_t* seg, int& nb) {
+  constexpr int KB = KnnBuf<KC>::KB;
+  int32_t p = rb;
+  for (; p + kGroup <= re; p += kGroup) {
+    float4 P[kGroup];
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) P[u] = load_const(cp, p + u);
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      const float dx = q.x - P[u].x, dy = q.y - P[u].y, dz = q.z - P[u].z;
+      const float D = (dx * dx + dy * dy) + dz * dz;
+      // D >= 0, so its bit pattern orders like its value; ties go to the
+      // lower original index in the low word
+      const uint64_t key = ((uint64_t)__float_as_uint(D) << 32) | (uint64_t)__float_as_uint(P[u].w);
+      if (KnnBuf<KC>::on) {
+        // written to the next free slot, kept only if accepted
+        seg[nb] = key;
+        nb += (D <= rmax2 && key < kthk) ? 1 : 0;
+      } else if (D <= rmax2 && key < best[KC - 1]) {
+        topk_insert<KC>(best, key);
+      }
+    }
+    if (KnnBuf<KC>::on && __ballot(nb > KB - kGroup)) {
+      merge_buffer<KC>(best, seg, nb);
+      kthk = kth_key<KC>(best, k);
+    }
+  }
+  for (; p < re; ++p) {
+    const float4 P = load_const(cp, p);
     const float dx = q.x - P.x, dy = q.y - P.y, dz = q.z - P.z;
     const float D = (dx * dx + dy * dy) + dz * dz;
-    // D >= 0, so its bit pattern orders like its value; ties go to the
-    // lower original index in the low word
     const uint64_t key = ((uint64_t)__float_as_uint(D) << 32) | (uint64_t)__float_as_uint(P.w);
-    if (D <= rmax2 && key < best[KC - 1]) topk_insert<KC>(best, key);
+    if (KnnBuf<KC>::on) {
+      seg[nb] = key;
+      nb += (D <= rmax2 && key < kthk) ? 1 : 0;
+    } else if (D <= rmax2 && key < best[KC - 1]) {
+      topk_insert<KC>(best, key);
+    }
+    if (KnnBuf<KC>::on && __ballot(nb > KB - kGroup)) {
+      merge_buffer<KC>(best, seg, nb);
+      kthk = kth_key<KC>(best, k);
+    }
   }
 }
 
 template <int KC, bool MULTI, int FL>
-__device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int lane) {
+__device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int lane,
+                                         uint64_t* seg) {
   const Grid g = MULTI ? A.W.tiles[it.tile] : A.g0;
   const int64_t t = it.t0 + lane;
   const bool in = t < it.tend;
@@ -577,73 +704,100 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
   const uint32_t qid = wq & ~kInactive;
   const bool active = in && !(wq & kInactive) && (int64_t)qid < A.W.nq;
   const Tile tb = tile_bounds(q, active);
+  const const_pts cp = as_const(A.pts);
+  // lanes without a valid query accept nothing
+  const float rmax2 = active ? A.rmax2 : -1.0f;
   uint64_t best[KC];
 #pragma unroll
   for (int i = 0; i < KC; ++i) best[i] = ~0ull;
+  uint64_t kthk = ~0ull;
+  int nb = 0;
   if (tb.any) {
-    // ring 0: the voxels holding the tile's queries (clamped into the grid)
-    VBox B;
-    B.empty = false;
+    // ring 0: the voxels holding the tile's queries (clamped into the grid);
+    // voxel coordinates fit 32 bits (fewer than 1e9 voxels per axis)
+    IBox B;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       if (a >= g.dims) {
         B.lo[a] = B.hi[a] = 0;
         continue;
       }
-      B.lo[a] = voxel_clamped((double)tb.lo[a], g.s[a], g.n[a]);
-      B.hi[a] = voxel_clamped((double)tb.hi[a], g.s[a], g.n[a]);
+      B.lo[a] = first_lane((int32_t)voxel_clamped((double)tb.lo[a], g.s[a], g.n[a]));
+      B.hi[a] = first_lane((int32_t)voxel_clamped((double)tb.hi[a], g.s[a], g.n[a]));
     }
-    VBox V;  // visited voxels (the taboo box)
-    V.empty = true;
+    IBox V;  // visited voxels (the taboo box)
+    bool vempty = true;
     const float qc[3] = {q.x, q.y, q.z};
+    // Points farther from the tile's query box than every unfinished lane's
+    // threshold can never enter a list (thresholds only shrink), so columns
+    // and z-ranges beyond that distance are skipped; +inf until every
+    // unfinished lane holds k keys.
+    double tau = INFINITY;
     while (true) {
+      int32_t kz0 = B.lo[2], kz1 = B.hi[2];
+      double padk = INFINITY;
+      if (tau < INFINITY) {
+        padk = fmax(sqrt(tau) * (1.0 + kPadRel), kPadAbs);
+        if (g.dims == 3) {
+          const double zlo = floor(((double)tb.lo[2] - padk) / g.s[2]);
+          const double zhi = floor(((double)tb.hi[2] + padk) / g.s[2]);
+          if (zlo > (double)kz0) kz0 = (int32_t)zlo;
+          if (zhi < (double)kz1) kz1 = (int32_t)zhi;
+          kz0 = first_lane(kz0);
+          kz1 = first_lane(kz1);
+        }
+      }
       // visit B minus V, column by column (one column per lane)
       const int64_t nj = B.hi[1] - B.lo[1] + 1;
-      const int64_t ncol = (B.hi[0] - B.lo[0] + 1) * nj;
+      const int64_t ncol = (int64_t)(B.hi[0] - B.lo[0] + 1) * nj;
       for (int64_t cb = 0; cb < ncol; cb += kWave) {
         const int64_t c = cb + lane;
         int32_t b0 = 0, e0 = 0, b1 = 0, e1 = 0;
-        if (c < ncol) {
+        if (c < ncol && kz0 <= kz1) {
           const int64_t ci = B.lo[0] + c / nj, cj = B.lo[1] + c % nj;
-          const bool inner = !V.empty && ci >= V.lo[0] && ci <= V.hi[0] && cj >= V.lo[1] &&
+          const bool inner = !vempty && ci >= V.lo[0] && ci <= V.hi[0] && cj >= V.lo[1] &&
                              cj <= V.hi[1];
-          if (!inner) {
-            column_run<FL>(A.vx, g, ci, cj, B.lo[2], B.hi[2], &b0, &e0);
-          } else {
-            if (B.lo[2] < V.lo[2]) column_run<FL>(A.vx, g, ci, cj, B.lo[2], V.lo[2] - 1, &b0, &e0);
-            if (B.hi[2] > V.hi[2]) column_run<FL>(A.vx, g, ci, cj, V.hi[2] + 1, B.hi[2], &b1, &e1);
+          if (padk == INFINITY || column_near(g, tb, ci, cj, padk)) {
+            if (!inner) {
+              column_run<FL>(A.vx, g, ci, cj, kz0, kz1, &b0, &e0);
+            } else {
+              const int32_t a1 = V.lo[2] - 1 < kz1 ? V.lo[2] - 1 : kz1;
+              const int32_t a2 = V.hi[2] + 1 > kz0 ? V.hi[2] + 1 : kz0;
+              if (kz0 <= a1) column_run<FL>(A.vx, g, ci, cj, kz0, a1, &b0, &e0);
+              if (a2 <= kz1) column_run<FL>(A.vx, g, ci, cj, a2, kz1, &b1, &e1);
+            }
           }
         }
         uint64_t m0 = __ballot(e0 > b0);
         while (m0) {
           const int src = __builtin_ctzll(m0);
           m0 &= m0 - 1;
-          scan_run<KC>(A.pts, __builtin_amdgcn_readlane(b0, src), __builtin_amdgcn_readlane(e0, src),
-                       q, A.rmax2, best);
+          knn_scan<KC>(cp, __builtin_amdgcn_readlane(b0, src), __builtin_amdgcn_readlane(e0, src),
+                       q, rmax2, A.k, best, kthk, seg, nb);
         }
         uint64_t m1 = __ballot(e1 > b1);
         while (m1) {
           const int src = __builtin_ctzll(m1);
           m1 &= m1 - 1;
-          scan_run<KC>(A.pts, __builtin_amdgcn_readlane(b1, src), __builtin_amdgcn_readlane(e1, src),
-                       q, A.rmax2, best);
+          knn_scan<KC>(cp, __builtin_amdgcn_readlane(b1, src), __builtin_amdgcn_readlane(e1, src),
+                       q, rmax2, A.k, best, kthk, seg, nb);
         }
       }
+      if (KnnBuf<KC>::on && __ballot(nb > 0)) merge_buffer<KC>(best, seg, nb);
+      kthk = kth_key<KC>(best, A.k);
       V = B;
+      vempty = false;
       // termination: every point outside V lies beyond the nearest face of V
       // that is not on the grid boundary; once the k-th best (or the radius
       // cap) is strictly below that distance squared, nothing outside V can
       // enter the list (ties included).
-      uint64_t kth = best[0];
-#pragma unroll
-      for (int i = 1; i < KC; ++i)
-        if (i == A.k - 1) kth = best[i];
       float thr = A.rmax2;
-      if (kth != ~0ull) {
-        const float dk = __uint_as_float((uint32_t)(kth >> 32));
+      if (kthk != ~0ull) {
+        const float dk = __uint_as_float((uint32_t)(kthk >> 32));
         thr = dk < thr ? dk : thr;
       }
       double lb = INFINITY;
+      bool whole = true;  // V is the whole grid (decided from V alone: uniform)
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         if (a >= g.dims) continue;
@@ -651,17 +805,20 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
         if (V.lo[a] > 0) {
           const double f = (double)V.lo[a] * g.s[a];
           lb = fmin(lb, (c - f) - 0x1p-50 * (fabs(c) + fabs(f)));
+          whole = false;
         }
         if (V.hi[a] < g.n[a] - 1) {
           const double f = (double)(V.hi[a] + 1) * g.s[a];
           lb = fmin(lb, (f - c) - 0x1p-50 * (fabs(c) + fabs(f)));
+          whole = false;
         }
       }
-      if (lb == INFINITY) break;  // V is the whole grid
+      if (whole) break;
       lb = fmax(lb, 0.0);
       const double lb2 = lb * lb;
       const bool done = !active || (lb2 >= 0x1p-100 && (double)thr < lb2 * (1.0 - kPadRel));
       if (__ballot(!done) == 0ull) break;
+      tau = wave_max(done ? -INFINITY : (double)thr);
       // next ring: grow the box by one voxel on every side
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -689,16 +846,19 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
 
 template <int KC, bool MULTI, int FL>
 __global__ __launch_bounds__(kThreads) void k_knn(KnnArgs A) {
+  constexpr int kSeg = KnnBuf<KC>::on ? kWave * KnnBuf<KC>::stride : 1;
+  __shared__ uint64_t s_buf[kWavesPerBlock * kSeg];
   const int w = threadIdx.x / kWave, lane = lane_id();
+  uint64_t* seg = s_buf + w * kSeg + (KnnBuf<KC>::on ? lane * KnnBuf<KC>::stride : 0);
   int64_t own = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
   if (!MULTI) {
-    if (own < A.W.nwaves) knn_item<KC, false, FL>(A, item_of(A.W, own), lane);
+    if (own < A.W.nwaves) knn_item<KC, false, FL>(A, item_of(A.W, own), lane, seg);
     return;
   }
   while (true) {
     const int64_t item = next_item(A.W, &own, lane);
     if (item >= A.W.nwaves) break;
-    knn_item<KC, true, FL>(A, item_of(A.W, item), lane);
+    knn_item<KC, true, FL>(A, item_of(A.W, item), lane, seg);
   }
 }
 
