@@ -54,6 +54,124 @@ def counter_traffic(kernel, radius):
     return ent
 
 
+# rocprofv3 runs whose summaries are committed under profiles/ (run from the
+# repository root, after `cd /tmp && export TMPDIR=/tmp`, with R the root)
+PROFILE_RUNS = {
+    "stats": "rocprofv3 --kernel-trace --stats -d $R/gpurun_out/prof_stats -o stats -- "
+             "python3 $R/bench.py --steps 5 --warmup 2 --no-cpu-baseline",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-trace -d $R/gpurun_out/prof_fetch -o fetch -- "
+             "python3 $R/bench.py --steps 1 --warmup 0 --radii 3 --ks 32 --no-cpu-baseline "
+             "--copy-calibration-mib 1024",
+    "write": "rocprofv3 --pmc WRITE_SIZE --kernel-trace -d $R/gpurun_out/prof_write -o write -- "
+             "python3 $R/bench.py --steps 1 --warmup 0 --radii 3 --ks 32 --no-cpu-baseline "
+             "--copy-calibration-mib 1024",
+}
+FILL_KERNEL = "k_radius<true"  # the single-tile fill (dense flavor)
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def _db(d):
+    import glob
+    import sqlite3
+    f = sorted(glob.glob(os.path.join(d, "**", "*.db"), recursive=True))
+    if not f:
+        raise SystemExit(f"no rocprofv3 database under {d}")
+    return sqlite3.connect(f[0])
+
+
+def _dispatches(con):
+    """(name, duration ms) of every kernel dispatch, in dispatch order."""
+    q = ("select S.display_name, K.start, K.end from rocpd_kernel_dispatch K join "
+         "rocpd_info_kernel_symbol S on S.id = K.kernel_id and S.guid = K.guid order by K.start")
+    return [(n, (e - b) / 1e6) for n, b, e in con.execute(q)]
+
+
+def _counter(con, counter):
+    """{dispatch_id: (kernel name, summed counter value)} for one counter."""
+    q = ("select dispatch_id, kernel_name, sum(value) from counters_collection "
+         "where counter_name = ? group by dispatch_id")
+    return {d: (n, v) for d, n, v in con.execute(q, (counter,))}
+
+
+def profile_summary(stats_dir, fetch_dir, write_dir, radii=(0.5, 1.0, 2.0, 3.0), n=10_000_000):
+    """Write the committed rocprofv3 summaries: per-kernel times of the
+    default bench step, and HBM traffic of the radius fill at r = 3 m from
+    FETCH_SIZE / WRITE_SIZE scaled by what the counters read for a 1 GiB
+    device copy."""
+    out_dir = os.path.join(ROOT, "profiles")
+    os.makedirs(out_dir, exist_ok=True)
+    # ---- kernel times
+    disp = _dispatches(_db(stats_dir))
+    agg = {}
+    for name, ms in disp:
+        a = agg.setdefault(name, [0, 0.0])
+        a[0] += 1
+        a[1] += ms
+    total = sum(v[1] for v in agg.values())
+    fills = [ms for name, ms in disp if FILL_KERNEL in name]
+    per_r = {r: fills[i::len(radii)] for i, r in enumerate(radii)}
+    lines = ["# Kernel times, default bench step (10 M-point ALS tile)", "",
+             "Command (from the repository root R, after `cd /tmp && export TMPDIR=/tmp`):", "",
+             "    " + PROFILE_RUNS["stats"], "",
+             "7 steps profiled (2 warm-up + 5 timed).  Per kernel: dispatches, total and "
+             "average duration.", "",
+             "| kernel | calls | total ms | avg ms | % |", "|---|---:|---:|---:|---:|"]
+    for name, (c, ms) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:25]:
+        lines.append(f"| `{name[:90]}` | {c} | {ms:.3f} | {ms / c:.4f} | {100 * ms / total:.1f} |")
+    lines += ["", "Radius fill (`%s`) by radius, average ms per launch:" % FILL_KERNEL, ""]
+    for r in radii:
+        v = per_r[r]
+        if v:
+            lines.append(f"- r = {r} m: {sum(v) / len(v):.3f} ms over {len(v)} launches")
+    with open(os.path.join(out_dir, "kernels_als10m.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    # ---- traffic of the fill at r = 3 m
+    fetch = _counter(_db(fetch_dir), "FETCH_SIZE")
+    write = _counter(_db(write_dir), "WRITE_SIZE")
+
+    def pick(cnt, key):
+        return [v for _, (name, v) in sorted(cnt.items()) if key in name]
+
+    gib = float(1 << 30)
+    # the calibration copy is the largest copy dispatch of the run
+    cf = sorted(pick(fetch, COPY_KERNEL))
+    cw = sorted(pick(write, COPY_KERNEL))
+    ff = pick(fetch, FILL_KERNEL)
+    fw = pick(write, FILL_KERNEL)
+    if not (cf and cw and ff and fw):
+        raise SystemExit("copy or fill kernel missing from the counter runs")
+    f_fac = gib / (cf[-1] * 1024.0)
+    w_fac = gib / (cw[-1] * 1024.0)
+    fill_read = ff[-1] * 1024.0 * f_fac
+    fill_write = fw[-1] * 1024.0 * w_fac
+    rec = {"kernel": "k_radius<fill>", "workload": "10 M-point ALS tile, r = 3 m, every point a query",
+           "commands": {"fetch": PROFILE_RUNS["fetch"], "write": PROFILE_RUNS["write"]},
+           "copy_calibration": {"bytes": 1 << 30, "fetch_kib": cf[-1], "write_kib": cw[-1],
+                                "fetch_factor": f_fac, "write_factor": w_fac},
+           "fill_counters_kib": {"fetch": ff[-1], "write": fw[-1]},
+           "fill_bytes": {"read": fill_read, "write": fill_write},
+           "source_hash": source_hash(),
+           "per_launch_bytes": {"k_radius<fill>@r=3.0": fill_read + fill_write}}
+    with open(os.path.join(out_dir, "radius_fill_als10m_pmc.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    md = ["# HBM traffic of the radius fill, r = 3 m (10 M-point ALS tile)", "",
+          "Commands (from the repository root R, after `cd /tmp && export TMPDIR=/tmp`):", "",
+          "    " + PROFILE_RUNS["fetch"], "    " + PROFILE_RUNS["write"], "",
+          "Calibration: one 1 GiB device copy (`%s`) reads FETCH_SIZE = %.0f KiB and "
+          "WRITE_SIZE = %.0f KiB, so the factors are %.4f (fetch) and %.4f (write)."
+          % (COPY_KERNEL, cf[-1], cw[-1], f_fac, w_fac), "",
+          "| | counter KiB | scaled bytes |", "|---|---:|---:|",
+          f"| read  | {ff[-1]:.0f} | {fill_read:.4g} |",
+          f"| write | {fw[-1]:.0f} | {fill_write:.4g} |",
+          f"| total | | {fill_read + fill_write:.4g} |", "",
+          "Kernel sources hash: `%s` (bench.py reports this traffic only while the "
+          "sources match)." % rec["source_hash"]]
+    with open(os.path.join(out_dir, "radius_fill_als10m_pmc.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print(json.dumps({"kernels": len(agg), "fill_r3_ms": per_r[radii[-1]],
+                      "fill_traffic": rec["per_launch_bytes"]}), flush=True)
+
+
 def cpu_baseline(xyz, radii, ks, cell, sample, nthreads):
     """The oracle as it stands, on the host cores: full build plus a seeded
     sample of queries per radius / k, scaled to the whole step."""
@@ -234,7 +352,12 @@ def main():
     ap.add_argument("--batch-r", type=float, default=1.0)
     ap.add_argument("--batch-k", type=int, default=16)
     ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--profile-summary", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write the profiles/ summaries from rocprofv3 output directories")
     args = ap.parse_args()
+    if args.profile_summary:
+        profile_summary(*args.profile_summary)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

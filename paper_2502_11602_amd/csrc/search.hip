@@ -559,14 +559,19 @@ struct KnnArgs {
 // merge per KB accepted candidates of its busiest lane instead of one
 // insertion for every candidate that any lane accepts.
 // Lists shorter than kKnnBufMin take the insertion directly: their
-// insertion network is short enough that buffering does not pay.
+// insertion network is short enough that buffering does not pay.  Longer
+// lists buffer kKnnBufLong keys, which keeps the merge's registers (list +
+// sorted buffer) within reach of three waves per SIMD.
 constexpr int kKnnBufMin = 16;
-constexpr int kKnnBufCap = 16;
+constexpr int kKnnBufLong = 8;
 template <int KC>
 struct KnnBuf {
   static constexpr bool on = KC >= kKnnBufMin;
-  static constexpr int KB = KC < kKnnBufCap ? KC : kKnnBufCap;  // buffered keys per lane
-  static constexpr int stride = KB + 1;  // odd, against bank conflicts
+  // candidates loaded together; buffered lists take small groups so that a
+  // merge is due only when some buffer is nearly full
+  static constexpr int group = on ? 2 : 4;
+  static constexpr int KB = KC <= 16 ? KC : kKnnBufLong;  // buffered keys per lane
+  static constexpr int stride = KB + 1;                   // odd, against bank conflicts
 };
 
 // Sorted insertion of key x < best[KC-1] into best[0..KC) (ascending),
@@ -650,13 +655,14 @@ __device__ __forceinline__ void knn_scan(const_pts cp, int32_t rb, int32_t re, f
                                          float rmax2, int k, uint64_t (&best)[KC], uint64_t& kthk,
                                          uint64_t* seg, int& nb) {
   constexpr int KB = KnnBuf<KC>::KB;
+  constexpr int kKnnGroup = KnnBuf<KC>::group;
   int32_t p = rb;
-  for (; p + kGroup <= re; p += kGroup) {
-    float4 P[kGroup];
+  for (; p + kKnnGroup <= re; p += kKnnGroup) {
+    float4 P[kKnnGroup];
 #pragma unroll
-    for (int u = 0; u < kGroup; ++u) P[u] = load_const(cp, p + u);
+    for (int u = 0; u < kKnnGroup; ++u) P[u] = load_const(cp, p + u);
 #pragma unroll
-    for (int u = 0; u < kGroup; ++u) {
+    for (int u = 0; u < kKnnGroup; ++u) {
       const float dx = q.x - P[u].x, dy = q.y - P[u].y, dz = q.z - P[u].z;
       const float D = (dx * dx + dy * dy) + dz * dz;
       // D >= 0, so its bit pattern orders like its value; ties go to the
@@ -670,7 +676,7 @@ __device__ __forceinline__ void knn_scan(const_pts cp, int32_t rb, int32_t re, f
         topk_insert<KC>(best, key);
       }
     }
-    if (KnnBuf<KC>::on && __ballot(nb > KB - kGroup)) {
+    if (KnnBuf<KC>::on && __ballot(nb > KB - kKnnGroup)) {
       merge_buffer<KC>(best, seg, nb);
       kthk = kth_key<KC>(best, k);
     }
@@ -686,7 +692,7 @@ __device__ __forceinline__ void knn_scan(const_pts cp, int32_t rb, int32_t re, f
     } else if (D <= rmax2 && key < best[KC - 1]) {
       topk_insert<KC>(best, key);
     }
-    if (KnnBuf<KC>::on && __ballot(nb > KB - kGroup)) {
+    if (KnnBuf<KC>::on && __ballot(nb > KB - kKnnGroup)) {
       merge_buffer<KC>(best, seg, nb);
       kthk = kth_key<KC>(best, k);
     }
