@@ -407,23 +407,35 @@ constexpr int kStage = 32;                 // entries per lane
 constexpr int kStageStride = kStage + 1;   // padded against LDS bank conflicts
 constexpr int kGroup = 4;                   // candidates loaded together in the fill
 
-__device__ __forceinline__ void flush_stage(const int32_t* seg_base, int lane, int& nb,
-                                            int64_t& wpos, int64_t wend,
+// Where a lane's staged entries go: the row position and how many of them
+// fit in the row (published once per flush, read by the half-waves).
+struct alignas(16) RowSlot {
+  int64_t pos;
+  int32_t cnt, pad_;
+};
+
+__device__ __forceinline__ void flush_stage(const int32_t* seg_base, RowSlot* rows, int lane,
+                                            int& nb, int64_t& wpos, int64_t wend,
                                             int32_t* __restrict__ nbr) {
+  const int64_t room = wend - wpos;
+  RowSlot slot;
+  slot.pos = wpos;
+  slot.cnt = room <= 0 ? 0 : (room < nb ? (int32_t)room : nb);
+  slot.pad_ = 0;
+  rows[lane] = slot;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   const int half = lane >> 5, i = lane & 31;
-  const uint64_t pending = __ballot(nb > 0);
-  // pairs of lanes (2m, 2m+1) with anything staged
+  const uint64_t pending = __ballot(slot.cnt > 0);
+  // pairs of lanes (2m, 2m+1) with anything staged: lanes 0-31 write lane
+  // 2m's run, lanes 32-63 lane 2m+1's, each a contiguous row segment
   uint64_t pairs = (pending | (pending >> 1)) & 0x5555555555555555ull;
   while (pairs) {
     const int m2 = __builtin_ctzll(pairs);
     pairs &= pairs - 1;
     const int src = m2 + half;
-    const int cnt = __shfl(nb, src, kWave);
-    const int64_t base = __shfl(wpos, src, kWave);
-    const int64_t end = __shfl(wend, src, kWave);
-    if (i < cnt && base + i < end) nbr[base + i] = seg_base[src * kStageStride + i];
+    const RowSlot r = rows[src];
+    if (i < r.cnt) nbr[r.pos + i] = seg_base[src * kStageStride + i];
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -433,7 +445,7 @@ __device__ __forceinline__ void flush_stage(const int32_t* seg_base, int lane, i
 
 template <bool FILL, bool MULTI, int FL>
 __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it, int lane,
-                                            int32_t* seg_base) {
+                                            int32_t* seg_base, RowSlot* rows) {
   const Grid g = MULTI ? A.W.tiles[it.tile] : A.g0;
   const int64_t t = it.t0 + lane;
   const bool in = t < it.tend;
@@ -501,7 +513,7 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
                 my_seg[nb] = __float_as_int(P[u].w) - poff;
                 nb += D <= R ? 1 : 0;
               }
-              if (__ballot(nb > kStage - kGroup)) flush_stage(seg_base, lane, nb, wpos, wend, A.nbr);
+              if (__ballot(nb > kStage - kGroup)) flush_stage(seg_base, rows, lane, nb, wpos, wend, A.nbr);
             }
             for (; p < re; ++p) {
               const float4 P = load_const(cp, p);
@@ -509,14 +521,14 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
               const float D = (dx * dx + dy * dy) + dz * dz;
               my_seg[nb] = __float_as_int(P.w) - poff;
               nb += D <= R ? 1 : 0;
-              if (__ballot(nb > kStage - kGroup)) flush_stage(seg_base, lane, nb, wpos, wend, A.nbr);
+              if (__ballot(nb > kStage - kGroup)) flush_stage(seg_base, rows, lane, nb, wpos, wend, A.nbr);
             }
           }
         }
       }
     }
   }
-  if (FILL) flush_stage(seg_base, lane, nb, wpos, wend, A.nbr);
+  if (FILL) flush_stage(seg_base, rows, lane, nb, wpos, wend, A.nbr);
   if (!FILL && in && (int64_t)qid < A.W.nq) A.counts[qid] = active ? cnt : 0;
 }
 
@@ -525,17 +537,19 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
 template <bool FILL, bool MULTI, int FL>
 __global__ __launch_bounds__(kThreads) void k_radius(RadiusArgs A) {
   __shared__ int32_t s_stage[FILL ? kWavesPerBlock * kWave * kStageStride : 1];
+  __shared__ RowSlot s_rows[FILL ? kWavesPerBlock * kWave : 1];
   const int w = threadIdx.x / kWave, lane = lane_id();
   int32_t* seg_base = s_stage + (FILL ? w * kWave * kStageStride : 0);
+  RowSlot* rows = s_rows + (FILL ? w * kWave : 0);
   int64_t own = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
   if (!MULTI) {
-    if (own < A.W.nwaves) radius_item<FILL, false, FL>(A, item_of(A.W, own), lane, seg_base);
+    if (own < A.W.nwaves) radius_item<FILL, false, FL>(A, item_of(A.W, own), lane, seg_base, rows);
     return;
   }
   while (true) {
     const int64_t item = next_item(A.W, &own, lane);
     if (item >= A.W.nwaves) break;
-    radius_item<FILL, true, FL>(A, item_of(A.W, item), lane, seg_base);
+    radius_item<FILL, true, FL>(A, item_of(A.W, item), lane, seg_base, rows);
   }
 }
 
@@ -626,6 +640,7 @@ __device__ __forceinline__ void bitonic_merge(uint64_t (&x)[N]) {
 // an indexed load from a memory copy of the list)
 template <int KC>
 __device__ __forceinline__ uint64_t kth_key(const uint64_t (&best)[KC], int k) {
+  if (KC <= 32 && k == KC) return best[KC - 1];  // k is uniform
   uint64_t v = 0;
 #pragma unroll
   for (int i = 0; i < KC; ++i) v |= best[i] & (0ull - (uint64_t)(i == k - 1));
