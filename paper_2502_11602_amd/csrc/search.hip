@@ -405,7 +405,8 @@ struct RadiusArgs {
 // partial lines.  Every store is also checked against its row's end.
 constexpr int kStage = 32;                 // entries per lane
 constexpr int kStageStride = kStage + 1;   // padded against LDS bank conflicts
-constexpr int kGroup = 4;                   // candidates loaded together in the fill
+constexpr int kGroup = 8;                   // candidates loaded together in the fill
+constexpr int kFlushUnroll = 4;             // lane pairs written per flush step
 
 // Where a lane's staged entries go: the row position and how many of them
 // fit in the row (published once per flush, read by the half-waves).
@@ -428,14 +429,33 @@ __device__ __forceinline__ void flush_stage(const int32_t* seg_base, RowSlot* ro
   const int half = lane >> 5, i = lane & 31;
   const uint64_t pending = __ballot(slot.cnt > 0);
   // pairs of lanes (2m, 2m+1) with anything staged: lanes 0-31 write lane
-  // 2m's run, lanes 32-63 lane 2m+1's, each a contiguous row segment
+  // 2m's run, lanes 32-63 lane 2m+1's, each a contiguous row segment.  A
+  // step takes kFlushUnroll pairs, so that all their LDS reads are in
+  // flight before the first store.
   uint64_t pairs = (pending | (pending >> 1)) & 0x5555555555555555ull;
   while (pairs) {
-    const int m2 = __builtin_ctzll(pairs);
-    pairs &= pairs - 1;
-    const int src = m2 + half;
-    const RowSlot r = rows[src];
-    if (i < r.cnt) nbr[r.pos + i] = seg_base[src * kStageStride + i];
+    int src[kFlushUnroll];
+    bool ok[kFlushUnroll];
+#pragma unroll
+    for (int u = 0; u < kFlushUnroll; ++u) {
+      ok[u] = pairs != 0;
+      src[u] = (ok[u] ? __builtin_ctzll(pairs) : 0) + half;
+      pairs &= pairs - 1;
+    }
+    RowSlot r[kFlushUnroll];
+    int32_t v[kFlushUnroll];
+#pragma unroll
+    for (int u = 0; u < kFlushUnroll; ++u) {
+      r[u] = rows[src[u]];
+      v[u] = seg_base[src[u] * kStageStride + i];
+    }
+    // keep the reads ahead of every store (the compiler would otherwise sink
+    // some of them into the stores' branches, one LDS round trip each)
+#pragma unroll
+    for (int u = 0; u < kFlushUnroll; ++u) asm volatile("" ::"v"(v[u]), "v"(r[u].pos), "v"(r[u].cnt));
+#pragma unroll
+    for (int u = 0; u < kFlushUnroll; ++u)
+      if (ok[u] && i < r[u].cnt) nbr[r[u].pos + i] = v[u];
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -865,10 +885,11 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
   }
 }
 
-// Lists of 32 run at four waves per SIMD: the few registers spilled cost
-// less than the latency hiding gained (measured on the 10 M-point tile).
+// Lists of 32 run at four waves per SIMD and lists of 8 at eight: the few
+// registers spilled cost less than the latency hiding gained (measured on
+// the 10 M-point tile).
 template <int KC, bool MULTI, int FL>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KC == 32 ? 4 : 1)))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KC == 32 ? 4 : (KC == 8 ? 8 : 1))))
 void k_knn(KnnArgs A) {
   constexpr int kSeg = KnnBuf<KC>::on ? kWave * KnnBuf<KC>::stride : 1;
   __shared__ uint64_t s_buf[kWavesPerBlock * kSeg];
