@@ -10,7 +10,9 @@ timed region; each call's results are produced in full (CSR neighbour lists,
 [Q,k] indices and squared distances).
 
 Prints one JSON line.  ``value`` is queries answered per second over the
-whole step (7 query batches of N queries, index build included).
+whole step (7 query batches of N queries, index build included).  After the
+timed steps, one step per voxel map (dense, sparse, mixed) is reported as
+the flavor comparison.
 """
 import argparse
 import hashlib
@@ -58,13 +60,13 @@ def counter_traffic(kernel, radius):
 # repository root, after `cd /tmp && export TMPDIR=/tmp`, with R the root)
 PROFILE_RUNS = {
     "stats": "rocprofv3 --kernel-trace --stats -d $R/gpurun_out/prof_stats -o stats -- "
-             "python3 $R/bench.py --steps 5 --warmup 2 --no-cpu-baseline",
+             "python3 $R/bench.py --steps 5 --warmup 2 --no-cpu-baseline --no-flavor-compare",
     "fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-trace -d $R/gpurun_out/prof_fetch -o fetch -- "
              "python3 $R/bench.py --steps 1 --warmup 0 --radii 3 --ks 32 --no-cpu-baseline "
-             "--copy-calibration-mib 1024",
+             "--no-flavor-compare --copy-calibration-mib 1024",
     "write": "rocprofv3 --pmc WRITE_SIZE --kernel-trace -d $R/gpurun_out/prof_write -o write -- "
              "python3 $R/bench.py --steps 1 --warmup 0 --radii 3 --ks 32 --no-cpu-baseline "
-             "--copy-calibration-mib 1024",
+             "--no-flavor-compare --copy-calibration-mib 1024",
 }
 FILL_KERNEL = "k_radius<true"  # the single-tile fill (dense flavor)
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
@@ -344,6 +346,7 @@ def main():
     ap.add_argument("--points", type=int, default=10_000_000)
     ap.add_argument("--cpu-sample", type=int, default=20_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-flavor-compare", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size before the steps "
                          "(a known-size kernel for scaling hardware byte counters)")
@@ -398,10 +401,10 @@ def main():
 
     E = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
 
-    def step(rec):
+    def step(rec, flavor=args.flavor):
         ev = {"start": E()}
         ev["start"].record()
-        ix = GridIndex(x, cell=args.cell, flavor=args.flavor)
+        ix = GridIndex(x, cell=args.cell, flavor=flavor)
         ev["build"] = E(); ev["build"].record()
         # the "every point" query order is planned by the first search on the
         # index and cached on it, so the first count below includes it
@@ -469,6 +472,22 @@ def main():
             "traffic": counter_traffic("k_radius<fill>", rdom),
             "algorithmic_bytes": alg_bytes, "launch_ms": phase[f"fill{rdom}"]}
 
+    # the three voxel maps on the same step, one warm and one measured step
+    # each, after the timed steps (config 1 compares the flavors)
+    flavors = {}
+    if not args.no_flavor_compare:
+        for fl in ("dense", "sparse", "mixed"):
+            step(None, fl)
+            rec = []
+            step(rec, fl)
+            torch.cuda.synchronize()
+            ev = rec[0][0]
+            el = {names[i]: ev[names[i - 1]].elapsed_time(ev[names[i]]) for i in range(1, len(names))}
+            flavors[fl] = {"build_ms": el["build"],
+                           "radius_ms": {str(r): el[f"count{r}"] + el[f"fill{r}"] for r in radii},
+                           "knn_ms": {str(k): el[f"knn{k}"] for k in ks}}
+            print(f"[bench] flavor {fl} done", file=sys.stderr, flush=True)
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -495,6 +514,7 @@ def main():
         "radius": radius,
         "knn": knn,
         "roofline": roof,
+        "flavors": flavors,
     }
     if not args.no_cpu_baseline:
         nth = len(os.sched_getaffinity(0))

@@ -595,7 +595,7 @@ struct KnnArgs {
 // Lists shorter than kKnnBufMin take the insertion directly: their
 // insertion network is short enough that buffering does not pay.  Longer
 // lists buffer kKnnBufLong keys, which keeps the merge's registers (list +
-// sorted buffer) within reach of three waves per SIMD.
+// sorted buffer) and the buffers' LDS small enough for several waves per SIMD.
 constexpr int kKnnBufMin = 16;
 constexpr int kKnnBufLong = 8;
 template <int KC>
@@ -604,7 +604,7 @@ struct KnnBuf {
   // candidates loaded together; buffered lists take small groups so that a
   // merge is due only when some buffer is nearly full
   static constexpr int group = on ? 2 : 4;
-  static constexpr int KB = KC <= 16 ? KC : kKnnBufLong;  // buffered keys per lane
+  static constexpr int KB = KC < 16 ? KC : kKnnBufLong;   // buffered keys per lane
   static constexpr int stride = KB + 1;                   // odd, against bank conflicts
 };
 
@@ -885,11 +885,11 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
   }
 }
 
-// Lists of 32 run at four waves per SIMD and lists of 8 at eight: the few
-// registers spilled cost less than the latency hiding gained (measured on
-// the 10 M-point tile).
+// Lists of 32 run at four waves per SIMD, of 16 at six and of 8 at eight:
+// the few registers spilled cost less than the latency hiding gained
+// (measured on the 10 M-point tile).
 template <int KC, bool MULTI, int FL>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KC == 32 ? 4 : (KC == 8 ? 8 : 1))))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KC == 32 ? 4 : (KC == 16 ? 6 : (KC == 8 ? 8 : 1)))))
 void k_knn(KnnArgs A) {
   constexpr int kSeg = KnnBuf<KC>::on ? kWave * KnnBuf<KC>::stride : 1;
   __shared__ uint64_t s_buf[kWavesPerBlock * kSeg];
