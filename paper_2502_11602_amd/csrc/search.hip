@@ -407,31 +407,38 @@ constexpr int kStage = 32;                 // entries per lane
 constexpr int kStageStride = kStage + 1;   // padded against LDS bank conflicts
 constexpr int kGroup = 8;                   // candidates loaded together in the fill
 constexpr int kFlushUnroll = 4;             // lane pairs written per flush step
+// A flush writes only the lanes holding at least kMinFlush entries (the
+// others keep theirs for the next flush), so that stores carry more entries.
+constexpr int kMinFlush = 12;
+static_assert(kMinFlush <= kStage - kGroup, "a kept run must leave room for a group");
 
 // Where a lane's staged entries go: the row position and how many of them
-// fit in the row (published once per flush, read by the half-waves).
+// are written (published once per flush, read by the half-waves).
 struct alignas(16) RowSlot {
   int64_t pos;
   int32_t cnt, pad_;
 };
 
+// FINAL: the lane's last flush, everything staged is written.
+template <bool FINAL>
 __device__ __forceinline__ void flush_stage(const int32_t* seg_base, RowSlot* rows, int lane,
                                             int& nb, int64_t& wpos, int64_t wend,
                                             int32_t* __restrict__ nbr) {
+  const int32_t used = (FINAL || nb >= kMinFlush) ? nb : 0;
   const int64_t room = wend - wpos;
   RowSlot slot;
   slot.pos = wpos;
-  slot.cnt = room <= 0 ? 0 : (room < nb ? (int32_t)room : nb);
+  slot.cnt = room <= 0 ? 0 : (room < used ? (int32_t)room : used);
   slot.pad_ = 0;
   rows[lane] = slot;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   const int half = lane >> 5, i = lane & 31;
-  const uint64_t pending = __ballot(slot.cnt > 0);
-  // pairs of lanes (2m, 2m+1) with anything staged: lanes 0-31 write lane
+  // pairs of lanes (2m, 2m+1) with entries to write: lanes 0-31 copy lane
   // 2m's run, lanes 32-63 lane 2m+1's, each a contiguous row segment.  A
-  // step takes kFlushUnroll pairs, so that all their LDS reads are in
-  // flight before the first store.
+  // step takes kFlushUnroll pairs, so that all their LDS reads are in flight
+  // before the first store.
+  const uint64_t pending = __ballot(slot.cnt > 0);
   uint64_t pairs = (pending | (pending >> 1)) & 0x5555555555555555ull;
   while (pairs) {
     int src[kFlushUnroll];
@@ -459,8 +466,8 @@ __device__ __forceinline__ void flush_stage(const int32_t* seg_base, RowSlot* ro
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  wpos += nb;
-  nb = 0;
+  wpos += used;
+  nb -= used;
 }
 
 template <bool FILL, bool MULTI, int FL>
@@ -533,7 +540,7 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
                 my_seg[nb] = __float_as_int(P[u].w) - poff;
                 nb += D <= R ? 1 : 0;
               }
-              if (__ballot(nb > kStage - kGroup)) flush_stage(seg_base, rows, lane, nb, wpos, wend, A.nbr);
+              if (__ballot(nb > kStage - kGroup)) flush_stage<false>(seg_base, rows, lane, nb, wpos, wend, A.nbr);
             }
             for (; p < re; ++p) {
               const float4 P = load_const(cp, p);
@@ -541,14 +548,14 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
               const float D = (dx * dx + dy * dy) + dz * dz;
               my_seg[nb] = __float_as_int(P.w) - poff;
               nb += D <= R ? 1 : 0;
-              if (__ballot(nb > kStage - kGroup)) flush_stage(seg_base, rows, lane, nb, wpos, wend, A.nbr);
+              if (__ballot(nb > kStage - kGroup)) flush_stage<false>(seg_base, rows, lane, nb, wpos, wend, A.nbr);
             }
           }
         }
       }
     }
   }
-  if (FILL) flush_stage(seg_base, rows, lane, nb, wpos, wend, A.nbr);
+  if (FILL) flush_stage<true>(seg_base, rows, lane, nb, wpos, wend, A.nbr);
   if (!FILL && in && (int64_t)qid < A.W.nq) A.counts[qid] = active ? cnt : 0;
 }
 

@@ -271,17 +271,22 @@ def test_knn_edge_cases():
 
 
 # ---------------------------------------------------------------- full size
+@pytest.fixture(scope="module")
+def config1_oracle():
+    c = cloudgen.config1()
+    return c, oracle.OracleIndex(c["xyz"], 1.0)
+
+
 @pytest.mark.slow
-def test_config1_full_size_sampled():
+def test_config1_full_size_sampled(config1_oracle):
     """The 10 M-point ALS tile, every point a query, in the launch
     configuration the benchmark times; a seeded sample of rows is checked
     against the oracle exactly, and the whole radius relation for symmetry."""
     dev = _dev()
-    c = cloudgen.config1()
+    c, ox = config1_oracle
     xyz = c["xyz"]
     n = len(xyz)
     gi = _gi()(torch.from_numpy(xyz).to(dev), cell=1.0)
-    ox = oracle.OracleIndex(xyz, 1.0)
     samp = np.sort(np.random.default_rng(42).choice(n, 3000, replace=False)).astype(np.int32)
     st = torch.from_numpy(samp.astype(np.int64)).to(dev)
     for r in c["radii"]:
@@ -313,3 +318,66 @@ def test_config1_full_size_sampled():
         oi, od = ox.knn(k, pidx=samp, nthreads=8)
         np.testing.assert_array_equal(idx[st].cpu().numpy(), oi)
         np.testing.assert_array_equal(d2[st].cpu().numpy(), od)
+
+
+@pytest.mark.slow
+def test_config1_full_size_knn_sampled(config1_oracle):
+    """k-NN at k = 8, 16, 32 on the 10 M-point tile, every point a query (the
+    benchmark's launches); a seeded sample of rows equals the oracle's, and
+    each k's list is a prefix of the next one's."""
+    dev = _dev()
+    c, ox = config1_oracle
+    xyz = c["xyz"]
+    gi = _gi()(torch.from_numpy(xyz).to(dev), cell=1.0)
+    samp = np.sort(np.random.default_rng(43).choice(len(xyz), 3000, replace=False)).astype(np.int32)
+    st = torch.from_numpy(samp.astype(np.int64)).to(dev)
+    prev = None
+    for k in c["ks"]:
+        idx, d2 = gi.knn(k)
+        oi, od = ox.knn(k, pidx=samp, nthreads=8)
+        np.testing.assert_array_equal(idx[st].cpu().numpy(), oi)
+        np.testing.assert_array_equal(d2[st].cpu().numpy(), od)
+        if prev is not None:
+            assert torch.equal(idx[:, :prev.shape[1]], prev)
+        prev = idx
+        del d2
+
+
+@pytest.fixture(scope="module")
+def config2_oracle():
+    c = cloudgen.config2()
+    return c, oracle.OracleIndex(c["xyz"], 0.25, flavor="sparse")
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("flavor", ["sparse", "mixed"])
+def test_config2_full_size_sampled(config2_oracle, flavor):
+    """The 20 M-point TLS scan (density falling with range), 0.25 m voxels:
+    k = 32 on all 2 M query indices, and radius at 0.1 / 0.25 / 0.5 m on
+    every 100th of them (near the scanner a 0.5 m ball holds tens of
+    thousands of points, so the CSR of all 2 M queries would not fit one
+    GPU); seeded samples of 2000 rows checked against the oracle."""
+    dev = _dev()
+    c, ox = config2_oracle
+    xyz = c["xyz"]
+    gi = _gi()(torch.from_numpy(xyz).to(dev), cell=0.25, flavor=flavor)
+    rq = c["queries"][::100]
+    q = torch.from_numpy(rq).to(dev)
+    sel = np.sort(np.random.default_rng(44).choice(len(rq), 2000, replace=False))
+    samp = rq[sel]
+    for r in c["radii"]:
+        off, nbr = gi.radius(r, q)
+        offc = off.cpu().numpy()
+        ooff, onbr = ox.radius(r, pidx=samp, nthreads=8)
+        np.testing.assert_array_equal(offc[sel + 1] - offc[sel], np.diff(ooff))
+        got = np.concatenate([np.sort(nbr[int(offc[t]):int(offc[t + 1])].cpu().numpy()) for t in sel])
+        want = np.concatenate([np.sort(onbr[ooff[j]:ooff[j + 1]]) for j in range(len(sel))])
+        np.testing.assert_array_equal(got, want)
+        del off, nbr
+    qa = torch.from_numpy(c["queries"]).to(dev)
+    idx, d2 = gi.knn(c["k"], qa)
+    sel = np.sort(np.random.default_rng(45).choice(len(c["queries"]), 2000, replace=False))
+    oi, od = ox.knn(c["k"], pidx=c["queries"][sel], nthreads=8)
+    st = torch.from_numpy(sel.astype(np.int64)).to(dev)
+    np.testing.assert_array_equal(idx[st].cpu().numpy(), oi)
+    np.testing.assert_array_equal(d2[st].cpu().numpy(), od)
