@@ -513,9 +513,13 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
           const int32_t rb = __builtin_amdgcn_readlane(b, src);
           const int32_t re = __builtin_amdgcn_readlane(e, src);
           if (!FILL) {
+            // read through the constant address space: in the persistent
+            // loop the work counter's atomic would otherwise turn these
+            // wave-uniform loads into vector loads
+            const_pts cp = as_const(A.pts);
 #pragma unroll 4
             for (int32_t p = rb; p < re; ++p) {
-              const float4 P = A.pts[p];
+              const float4 P = load_const(cp, p);
               const float dx = q.x - P.x, dy = q.y - P.y, dz = q.z - P.z;
               const float D = (dx * dx + dy * dy) + dz * dz;
               cnt += D <= R ? 1 : 0;
