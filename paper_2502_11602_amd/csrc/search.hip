@@ -654,15 +654,26 @@ __device__ __forceinline__ void bitonic_sort(uint64_t (&x)[N]) {
       }
 }
 
-// x bitonic -> x ascending
-template <int N>
+// Eight keys ascending with 19 compare-exchanges (the optimal network for
+// eight inputs; bitonic sorting takes 24).
+__device__ __forceinline__ void sort8(uint64_t (&x)[8]) {
+  constexpr int net[19][2] = {{0, 2}, {1, 3}, {4, 6}, {5, 7}, {0, 4}, {1, 5}, {2, 6},
+                              {3, 7}, {0, 1}, {2, 3}, {4, 5}, {6, 7}, {2, 4}, {3, 5},
+                              {1, 4}, {3, 6}, {1, 2}, {3, 4}, {5, 6}};
+#pragma unroll
+  for (int c = 0; c < 19; ++c) cmp_swap(x[net[c][0]], x[net[c][1]]);
+}
+
+// x bitonic -> x ascending.  x[0..P) is known to be ascending already, so
+// first-stage pairs that lie inside it are in order and skipped.
+template <int N, int P>
 __device__ __forceinline__ void bitonic_merge(uint64_t (&x)[N]) {
 #pragma unroll
   for (int j = N >> 1; j > 0; j >>= 1)
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       const int l = i ^ j;
-      if (l > i) cmp_swap(x[i], x[l]);
+      if (l > i && !(j == N / 2 && l < P)) cmp_swap(x[i], x[l]);
     }
 }
 
@@ -687,10 +698,12 @@ __device__ __forceinline__ void merge_buffer(uint64_t (&best)[KC], const uint64_
   uint64_t b[KB];
 #pragma unroll
   for (int i = 0; i < KB; ++i) b[i] = i < nb ? seg[i] : ~0ull;
-  bitonic_sort<KB>(b);
+  if constexpr (KB == 8) sort8(b);
+  else bitonic_sort<KB>(b);
 #pragma unroll
   for (int j = 0; j < KB; ++j) best[KC - 1 - j] = b[j] < best[KC - 1 - j] ? b[j] : best[KC - 1 - j];
-  bitonic_merge<KC>(best);
+  // best[0 .. KC-KB) was not touched and is still ascending
+  bitonic_merge<KC, KC - KB>(best);
   nb = 0;
 }
 
