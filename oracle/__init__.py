@@ -56,6 +56,8 @@ def lib():
         L.orc_slices.argtypes = [P, P, P]
         L.orc_radius.restype = P
         L.orc_radius.argtypes = [P, P, P, i64, f32, ctypes.c_int, P, P]
+        L.orc_kernel_search.restype = P
+        L.orc_kernel_search.argtypes = [P, P, P, i64, ctypes.c_int, f32, ctypes.c_int, P, P]
         L.orc_radius_copy.argtypes = [P, P]
         L.orc_radius_free.argtypes = [P]
         L.orc_knn.restype = ctypes.c_int
@@ -143,17 +145,20 @@ class OracleIndex:
             return None, qxyz, qxyz.shape[0]
         return None, None, None
 
-    def radius(self, r, pidx=None, qxyz=None, nthreads=1, visited=False):
-        """Alg. 1 with a sphere of radius ``r`` (FP32) per query; returns CSR
-        (offsets [nq+1], original point indices)."""
+    KERNELS = {"sphere": 0, "cube": 1, "cylinder": 2}
+
+    def radius(self, r, pidx=None, qxyz=None, nthreads=1, visited=False, kernel="sphere"):
+        """Alg. 1 per query with a closed sphere of radius ``r`` (FP32), or a
+        cube of half side r, or a vertical cylinder of radius r (z ignored);
+        returns CSR (offsets [nq+1], original point indices)."""
         pidx, qxyz, nq = self._queries(pidx, qxyz)
         if nq is None:
             nq = self.n
         L = lib()
         off = np.zeros(nq + 1, np.int64)
         vis = np.zeros(nq, np.int64) if visited else None
-        res = L.orc_radius(self._h, _p(pidx), _p(qxyz), nq, ctypes.c_float(r), nthreads, _p(off),
-                           _p(vis))
+        res = L.orc_kernel_search(self._h, _p(pidx), _p(qxyz), nq, self.KERNELS[kernel],
+                                  ctypes.c_float(r), nthreads, _p(off), _p(vis))
         nbr = np.zeros(int(off[-1]), np.int32)
         L.orc_radius_copy(res, _p(nbr))
         L.orc_radius_free(res)

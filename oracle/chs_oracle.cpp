@@ -12,7 +12,8 @@
 //   * global voxel index g = i*n_y*n_z + j*n_z + k          (Section 3.3.1, Eq. 6-7)
 //   * reordering of the points by voxel (counting sort)     (Section 3.5, "Reordering")
 //   * dense / sparse / mixed voxel storage                  (Section 3.3.1-3.3.3)
-//   * kernel-based (sphere) search                          (Section 3.4.1, Alg. 1)
+//   * kernel-based search: sphere, cube, cylinder           (Section 3.4.1, Alg. 1;
+//                                                            Section 2)
 //   * k-NN search with taboo box, sorted capped candidate
 //     list and density-based radius growth                  (Section 3.4.2, Alg. 2;
 //                                                            Section 3.5)
@@ -140,10 +141,17 @@ struct Box {
   bool empty;
 };
 
-// Voxel box covering the bounding box of B(c, r) (Section 3.4.1, Eq. 8-9),
-// padded by a relative 2^-18 (floor 2^-60) so that FP32 rounding of the
-// distance can never admit a point lying in a voxel outside the box.
-Box kernel_box(const OIndex& ix, const double c[3], double r) {
+// Search kernels (Section 3.4.1 and Section 2): a closed sphere, a cube
+// (L-infinity ball, half side r) and a vertical cylinder (disc of radius r,
+// z ignored).  Each gives a bounding box and an inside test (the paper's
+// box() / is_inside() pair); Alg. 1 is the same for all of them.
+enum Kernel { kSphere = 0, kCube = 1, kCylinder = 2 };
+
+// Voxel box covering the bounding box of the kernel around c (Section
+// 3.4.1, Eq. 8-9), padded by a relative 2^-18 (floor 2^-60) so that FP32
+// rounding can never admit a point lying in a voxel outside the box.  The
+// cylinder's box spans every z voxel.
+Box kernel_box(const OIndex& ix, const double c[3], double r, int kernel = kSphere) {
   Box b;
   b.empty = false;
   double pad = std::max(r * (1.0 + kPadRel), kPadAbs);
@@ -151,6 +159,11 @@ Box kernel_box(const OIndex& ix, const double c[3], double r) {
     if (a == 2 && ix.dims == 2) {
       b.lo[2] = 0;
       b.hi[2] = 0;
+      continue;
+    }
+    if (a == 2 && kernel == kCylinder) {
+      b.lo[2] = 0;
+      b.hi[2] = ix.ncell[2] - 1;
       continue;
     }
     if (!axis_range(c[a] - pad, c[a] + pad, ix.s[a], ix.ncell[a], &b.lo[a], &b.hi[a])) {
@@ -174,12 +187,29 @@ void query_coords(const OIndex& ix, const int32_t* pidx, const double* qxyz, int
   }
 }
 
-// ---- Alg. 1: kernel-based search with a spherical kernel -----------------
+// is_inside for each kernel, in FP32 like the distance: differences
+// fl32(c - p); sphere D <= fl32(r*r); cube |dx|, |dy|, |dz| <= r; cylinder
+// fl32(dx*dx + dy*dy) <= fl32(r*r), unfused.
+bool is_inside(int kernel, const float c[3], float px, float py, float pz, float r, float R) {
+  if (kernel == kCube) {
+    const float dx = c[0] - px, dy = c[1] - py, dz = c[2] - pz;
+    return std::fabs(dx) <= r && std::fabs(dy) <= r && std::fabs(dz) <= r;
+  }
+  if (kernel == kCylinder) {
+    const float dx = c[0] - px, dy = c[1] - py;
+    const float dx2 = dx * dx, dy2 = dy * dy;
+    const float h = dx2 + dy2;
+    return h <= R;
+  }
+  return sqdist(c[0], c[1], c[2], px, py, pz) <= R;  // closed sphere
+}
+
+// ---- Alg. 1: kernel-based search -----------------------------------------
 void radius_one(const OIndex& ix, const float c32[3], float r, std::vector<int32_t>& outv,
-                int64_t* visited) {
+                int64_t* visited, int kernel = kSphere) {
   const float R = r * r;  // fl32(r*r)
   double c[3] = {c32[0], c32[1], c32[2]};
-  Box b = kernel_box(ix, c, (double)r);
+  Box b = kernel_box(ix, c, (double)r, kernel);
   int64_t nvis = 0;
   if (!b.empty) {
     for (int64_t i = b.lo[0]; i <= b.hi[0]; ++i)
@@ -188,10 +218,9 @@ void radius_one(const OIndex& ix, const float c32[3], float r, std::vector<int32
           Range rg;
           if (!lookup(ix, i, j, k, &rg)) continue;  // voxel does not exist
           ++nvis;
-          for (int64_t p = rg.begin; p < rg.end; ++p) {
-            float D = sqdist(c32[0], c32[1], c32[2], ix.sx[0][p], ix.sx[1][p], ix.sx[2][p]);
-            if (D <= R) outv.push_back(ix.perm[p]);  // is_inside: closed sphere
-          }
+          for (int64_t p = rg.begin; p < rg.end; ++p)
+            if (is_inside(kernel, c32, ix.sx[0][p], ix.sx[1][p], ix.sx[2][p], r, R))
+              outv.push_back(ix.perm[p]);
         }
   }
   if (visited) *visited = nvis;
@@ -487,8 +516,8 @@ int64_t orc_slices(const void* h, int64_t* nonempty, uint8_t* dense) {
 
 // Queries: pidx = point indices into the cloud, or qxyz = FP64 absolute
 // coordinates [nq,3], or both NULL = every point of the cloud in index order.
-void* orc_radius(const void* h, const int32_t* pidx, const double* qxyz, int64_t nq, float r,
-                 int nthreads, int64_t* offsets, int64_t* visited) {
+void* orc_kernel_search(const void* h, const int32_t* pidx, const double* qxyz, int64_t nq,
+                        int kernel, float r, int nthreads, int64_t* offsets, int64_t* visited) {
   const OIndex* ix = static_cast<const OIndex*>(h);
   std::vector<std::vector<int32_t>> part((size_t)std::max(1, nthreads));
   std::vector<int64_t> cnt(nq, 0);
@@ -500,7 +529,7 @@ void* orc_radius(const void* h, const int32_t* pidx, const double* qxyz, int64_t
       float c[3];
       query_coords(*ix, pidx, qxyz, q, c);
       size_t before = out.size();
-      radius_one(*ix, c, r, out, visited ? visited + q : nullptr);
+      radius_one(*ix, c, r, out, visited ? visited + q : nullptr, kernel);
       cnt[q] = (int64_t)(out.size() - before);
     }
   });
@@ -510,6 +539,11 @@ void* orc_radius(const void* h, const int32_t* pidx, const double* qxyz, int64_t
   res->nbr.reserve(offsets[nq]);
   for (auto& v : part) res->nbr.insert(res->nbr.end(), v.begin(), v.end());
   return res;
+}
+
+void* orc_radius(const void* h, const int32_t* pidx, const double* qxyz, int64_t nq, float r,
+                 int nthreads, int64_t* offsets, int64_t* visited) {
+  return orc_kernel_search(h, pidx, qxyz, nq, kSphere, r, nthreads, offsets, visited);
 }
 
 void orc_radius_copy(void* res, int32_t* nbr) {

@@ -53,3 +53,31 @@ def brute_knn(pts32, q32, k, r_max=np.inf, block=256):
 
 def csr_rows(off, nbr):
     return [np.sort(nbr[off[i]:off[i + 1]]) for i in range(len(off) - 1)]
+
+
+def brute_kernel(pts32, q32, r, kernel, block=256):
+    """Like brute_radius for the other kernels of Alg. 1: a cube of half side
+    r (|dx|, |dy|, |dz| <= r) or a vertical cylinder of radius r
+    (fl32(dx^2 + dy^2) <= fl32(r*r), z ignored); dx = fl32(qx - px)."""
+    if kernel == "sphere":
+        return brute_radius(pts32, q32, r, block)
+    r32 = np.float32(r)
+    R = r32 * r32
+    pts = np.asarray(pts32, np.float32)
+    out = []
+    for a in range(0, q32.shape[0], block):
+        q = np.asarray(q32[a:a + block], np.float32)
+        dx = np.subtract(q[:, None, 0], pts[None, :, 0], dtype=np.float32)
+        dy = np.subtract(q[:, None, 1], pts[None, :, 1], dtype=np.float32)
+        if kernel == "cube":
+            dz = np.subtract(q[:, None, 2], pts[None, :, 2], dtype=np.float32)
+            m = (np.abs(dx) <= r32) & (np.abs(dy) <= r32) & (np.abs(dz) <= r32)
+        elif kernel == "cylinder":
+            h = np.add(np.multiply(dx, dx, dtype=np.float32), np.multiply(dy, dy, dtype=np.float32),
+                       dtype=np.float32)
+            m = h <= R
+        else:
+            raise ValueError(kernel)
+        for row in m:
+            out.append(np.nonzero(row)[0].astype(np.int32))
+    return out

@@ -9,7 +9,7 @@ import pytest
 
 import cloudgen
 import oracle
-from tests._brute import brute_knn, brute_radius, csr_rows, sq_dist_rows
+from tests._brute import brute_kernel, brute_knn, brute_radius, csr_rows, sq_dist_rows
 from tests.conftest import golden
 
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
@@ -202,6 +202,50 @@ def test_radius_equals_brute_force(name, flavor, dims, s):
         want = brute_radius(pts, pts[q], r)
         for a, b in zip(got, want):
             np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("kernel", ["cube", "cylinder"])
+@pytest.mark.parametrize("name", sorted(CLOUDS))
+@pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
+@pytest.mark.parametrize("dims,s", [(3, 0.5), (3, 1.0), (2, 2.5)])
+def test_other_kernels_equal_brute_force(kernel, name, flavor, dims, s):
+    """Alg. 1 with the cube and cylinder kernels (Section 2, Section 3.4.1)
+    against brute force, point and coordinate queries, r = 0 included."""
+    xyz = CLOUDS[name](6)
+    ix = oracle.OracleIndex(xyz, s, dims=dims, flavor=flavor)
+    pts = ix.point_arrays()["x32"].T
+    rng = np.random.default_rng(3)
+    q = rng.choice(len(xyz), 100, replace=False).astype(np.int32)
+    qa = rng.uniform(xyz.min(0) - 2.0, xyz.max(0) + 2.0, (60, 3))
+    for r in (0.0, 0.35, 1.0, 2.5):
+        off, nbr = ix.radius(r, pidx=q, kernel=kernel)
+        for a, b in zip(csr_rows(off, nbr), brute_kernel(pts, pts[q], r, kernel)):
+            np.testing.assert_array_equal(a, b)
+        off, nbr = ix.radius(r, qxyz=qa, kernel=kernel)
+        for a, b in zip(csr_rows(off, nbr), brute_kernel(pts, _q32(ix, qa), r, kernel)):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_cylinder_ignores_z_and_contains_the_sphere():
+    """A cylinder query's rows do not depend on the query's z, even far
+    outside the cloud's z range; the sphere's rows are subsets (exactly, in
+    FP32: adding fl32(dz^2) >= 0 cannot lower the sum)."""
+    xyz = _als(9)
+    ix = oracle.OracleIndex(xyz, 1.0)
+    rng = np.random.default_rng(4)
+    qa = xyz[rng.choice(len(xyz), 150, replace=False)].copy()
+    for r in (0.5, 2.0):
+        off0, nbr0 = ix.radius(r, qxyz=qa, kernel="cylinder")
+        for dz in (-37.0, 55.5):
+            qz = qa.copy()
+            qz[:, 2] += dz
+            off1, nbr1 = ix.radius(r, qxyz=qz, kernel="cylinder")
+            for a, b in zip(csr_rows(off0, nbr0), csr_rows(off1, nbr1)):
+                np.testing.assert_array_equal(a, b)
+        offs, nbrs = ix.radius(r, qxyz=qa)
+        for a, b in zip(csr_rows(offs, nbrs), csr_rows(off0, nbr0)):
+            assert np.isin(a, b).all()
+        assert (np.diff(off0) >= np.diff(offs)).all()
 
 
 @pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
