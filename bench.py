@@ -12,7 +12,7 @@ timed region; each call's results are produced in full (CSR neighbour lists,
 Prints one JSON line.  ``value`` is queries answered per second over the
 whole step (7 query batches of N queries, index build included).  After the
 timed steps, one step per voxel map (dense, sparse, mixed) is reported as
-the flavor comparison.
+the flavor comparison, and the cube and cylinder kernels per radius.
 """
 import argparse
 import hashlib
@@ -60,13 +60,14 @@ def counter_traffic(kernel, radius):
 # repository root, after `cd /tmp && export TMPDIR=/tmp`, with R the root)
 PROFILE_RUNS = {
     "stats": "rocprofv3 --kernel-trace --stats -d $R/gpurun_out/prof_stats -o stats -- "
-             "python3 $R/bench.py --steps 5 --warmup 2 --no-cpu-baseline --no-flavor-compare",
+             "python3 $R/bench.py --steps 5 --warmup 2 --no-cpu-baseline --no-flavor-compare "
+             "--no-kernel-compare",
     "fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-trace -d $R/gpurun_out/prof_fetch -o fetch -- "
              "python3 $R/bench.py --steps 1 --warmup 0 --radii 3 --ks 32 --no-cpu-baseline "
-             "--no-flavor-compare --copy-calibration-mib 1024",
+             "--no-flavor-compare --no-kernel-compare --copy-calibration-mib 1024",
     "write": "rocprofv3 --pmc WRITE_SIZE --kernel-trace -d $R/gpurun_out/prof_write -o write -- "
              "python3 $R/bench.py --steps 1 --warmup 0 --radii 3 --ks 32 --no-cpu-baseline "
-             "--no-flavor-compare --copy-calibration-mib 1024",
+             "--no-flavor-compare --no-kernel-compare --copy-calibration-mib 1024",
 }
 FILL_KERNEL = "k_radius<true"  # the single-tile fill (dense flavor)
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
@@ -347,6 +348,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=20_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-flavor-compare", action="store_true")
+    ap.add_argument("--no-kernel-compare", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size before the steps "
                          "(a known-size kernel for scaling hardware byte counters)")
@@ -488,6 +490,25 @@ def main():
                            "knn_ms": {str(k): el[f"knn{k}"] for k in ks}}
             print(f"[bench] flavor {fl} done", file=sys.stderr, flush=True)
 
+    # the cube and cylinder kernels of Alg. 1 on the same tile (outside the
+    # timed steps): count + fill per radius, one warm and one measured pass
+    shapes = {}
+    if not args.no_kernel_compare:
+        ix = GridIndex(x, cell=args.cell, flavor=args.flavor)
+        for kern in ("cube", "cylinder"):
+            shapes[kern] = {}
+            for r in radii:
+                for rep in range(2):
+                    a, b = E(), E()
+                    a.record()
+                    off, nbr = ix.radius(r, kernel=kern)
+                    b.record()
+                    torch.cuda.synchronize()
+                shapes[kern][str(r)] = {"ms": a.elapsed_time(b), "neighbours": int(nbr.numel())}
+                del off, nbr
+        ix.close()
+        print("[bench] cube / cylinder done", file=sys.stderr, flush=True)
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -515,6 +536,7 @@ def main():
         "knn": knn,
         "roofline": roof,
         "flavors": flavors,
+        "kernels": shapes,
     }
     if not args.no_cpu_baseline:
         nth = len(os.sched_getaffinity(0))

@@ -194,6 +194,29 @@ chs_status chs_radius_search(chs_index index, const chs_queries* queries, float 
                              const chs_allocator* alloc, int64_t* offsets, int32_t** nbr,
                              int64_t* total, hipStream_t stream);
 
+/* Other kernels of Alg. 1 (Section 3.4.1: the search works for any kernel
+ * that gives a bounding box and an inside test; the cube and the cylinder of
+ * Section 2).  With differences dx = fl32(qx - px) etc. and R = fl32(r*r):
+ *   CHS_KERNEL_SPHERE    (dx*dx + dy*dy) + dz*dz <= R  (the chs_radius_* calls)
+ *   CHS_KERNEL_CUBE      |dx| <= r and |dy| <= r and |dz| <= r  (half side r)
+ *   CHS_KERNEL_CYLINDER  dx*dx + dy*dy <= R, any z (a vertical cylinder)
+ * all in FP32 with unfused operations.  Arguments, outputs, ownership and
+ * errors as chs_radius_count / chs_radius_fill / chs_radius_search; an
+ * unknown kernel is CHS_E_INVALID. */
+typedef enum chs_kernel {
+  CHS_KERNEL_SPHERE = 0,
+  CHS_KERNEL_CUBE = 1,
+  CHS_KERNEL_CYLINDER = 2
+} chs_kernel;
+chs_status chs_kernel_count(chs_index index, const chs_queries* queries, int32_t kernel, float r,
+                            int64_t* offsets, int64_t* total, hipStream_t stream);
+chs_status chs_kernel_fill(chs_index index, const chs_queries* queries, int32_t kernel, float r,
+                           const int64_t* offsets, int32_t* nbr, int64_t total,
+                           hipStream_t stream);
+chs_status chs_kernel_search(chs_index index, const chs_queries* queries, int32_t kernel, float r,
+                             const chs_allocator* alloc, int64_t* offsets, int32_t** nbr,
+                             int64_t* total, hipStream_t stream);
+
 /* k-nearest-neighbour search (Section 3.4.2): for every query, the min(k, n)
  * points first in the order (D, original index), written to idx [nq,k]
  * (int32) and their squared distances D to d2 [nq,k] (FP32), ascending;

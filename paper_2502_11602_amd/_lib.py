@@ -60,6 +60,13 @@ SIGNATURES = {
     "chs_radius_search": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_float,
                                     ctypes.POINTER(Allocator), c_void_p, ctypes.POINTER(c_void_p),
                                     ctypes.POINTER(c_int64), c_void_p]),
+    "chs_kernel_count": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_int32, c_float, c_void_p,
+                                   ctypes.POINTER(c_int64), c_void_p]),
+    "chs_kernel_fill": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_int32, c_float, c_void_p,
+                                  c_void_p, c_int64, c_void_p]),
+    "chs_kernel_search": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_int32, c_float,
+                                    ctypes.POINTER(Allocator), c_void_p, ctypes.POINTER(c_void_p),
+                                    ctypes.POINTER(c_int64), c_void_p]),
     "chs_knn": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_int32, c_float, c_void_p, c_void_p,
                           c_void_p]),
     "chs_gauss_agg_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_int32,

@@ -344,6 +344,12 @@ struct IBox {
 
 // Voxel box covering [lo - pad, hi + pad] along every indexed axis, clamped
 // to the grid; empty when it misses the grid.
+// Search kernels of Alg. 1 (Section 3.4.1; the cube and the cylinder of
+// Section 2): each gives the box around the queries and an inside test.
+enum KernelShape { kSphere = 0, kCube = 1, kCylinder = 2 };
+
+// KS: the cylinder's box spans every z voxel
+template <int KS = kSphere>
 __device__ __forceinline__ VBox voxel_box(const Grid& g, const float* lo, const float* hi,
                                           double pad) {
   VBox b;
@@ -352,6 +358,11 @@ __device__ __forceinline__ VBox voxel_box(const Grid& g, const float* lo, const 
     if (a >= g.dims) {
       b.lo[a] = 0;
       b.hi[a] = 0;
+      continue;
+    }
+    if (KS == kCylinder && a == 2) {
+      b.lo[2] = 0;
+      b.hi[2] = g.n[2] - 1;
       continue;
     }
     const double clo = floor(((double)lo[a] - pad) / g.s[a]);
@@ -386,6 +397,22 @@ __device__ __forceinline__ bool column_near(const Grid& g, const Tile& t, int64_
 }
 
 // ---------------------------------------------------------------- radius search
+// Inside test in FP32 with unfused operations, differences fl32(q - p):
+// sphere (dx*dx + dy*dy) + dz*dz <= R, cube |dx|, |dy|, |dz| <= r, cylinder
+// dx*dx + dy*dy <= R, where R = fl32(r*r).  Lanes without a valid query pass
+// r = R = -1, which nothing satisfies.
+template <int KS>
+__device__ __forceinline__ bool inside(float4 q, float4 P, float r, float R) {
+  const float dx = q.x - P.x, dy = q.y - P.y;
+  if (KS == kCube) {
+    const float dz = q.z - P.z;
+    return fabsf(dx) <= r && fabsf(dy) <= r && fabsf(dz) <= r;
+  }
+  if (KS == kCylinder) return dx * dx + dy * dy <= R;
+  const float dz = q.z - P.z;
+  return (dx * dx + dy * dy) + dz * dz <= R;
+}
+
 struct RadiusArgs {
   Waves W;
   Grid g0;  // the grid of a single-tile index
@@ -398,11 +425,12 @@ struct RadiusArgs {
 };
 
 // Fill-pass staging: each lane appends its matches to a private LDS
-// segment; when any segment is full the wave flushes them all, writing each
-// lane's segment to that lane's CSR row as one contiguous run (two rows per
-// store instruction, one per half-wave) instead of 64 scattered 4-byte
-// stores per candidate, which the memory system would write back as 64
-// partial lines.  Every store is also checked against its row's end.
+// segment; when some segment could overflow in the next group of
+// candidates, the wave flushes the segments, writing each lane's entries to
+// that lane's CSR row as one contiguous run (two rows per store
+// instruction, one per half-wave) instead of 64 scattered 4-byte stores per
+// candidate, which the memory system would write back as 64 partial lines.
+// Every store is also checked against its row's end.
 constexpr int kStage = 32;                 // entries per lane
 constexpr int kStageStride = kStage + 1;   // padded against LDS bank conflicts
 constexpr int kGroup = 8;                   // candidates loaded together in the fill
@@ -470,7 +498,7 @@ __device__ __forceinline__ void flush_stage(const int32_t* seg_base, RowSlot* ro
   nb -= used;
 }
 
-template <bool FILL, bool MULTI, int FL>
+template <bool FILL, bool MULTI, int FL, int KS>
 __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it, int lane,
                                             int32_t* seg_base, RowSlot* rows) {
   const Grid g = MULTI ? A.W.tiles[it.tile] : A.g0;
@@ -481,9 +509,11 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
   const uint32_t qid = wq & ~kInactive;
   const bool active = in && !(wq & kInactive) && (int64_t)qid < A.W.nq;
   const Tile tb = tile_bounds(q, active);
-  // fl32(r*r); lanes without a valid query get a negative bound so that no
-  // candidate (D >= 0, or NaN) ever matches for them and they write nothing
+  // fl32(r*r); lanes without a valid query get negative bounds so that no
+  // candidate (D >= 0, |d| >= 0, or NaN) ever matches for them and they
+  // write nothing
   const float R = active ? A.r * A.r : -1.0f;
+  const float rr = active ? A.r : -1.0f;
   const double pad = fmax((double)A.r * (1.0 + kPadRel), kPadAbs);
   const int32_t poff = (int32_t)g.poff;
   int32_t cnt = 0;
@@ -495,7 +525,7 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
     wend = A.offsets[qid + 1];
   }
   if (tb.any) {
-    const VBox bx = voxel_box(g, tb.lo, tb.hi, pad);
+    const VBox bx = voxel_box<KS>(g, tb.lo, tb.hi, pad);
     if (!bx.empty) {
       const int64_t nj = bx.hi[1] - bx.lo[1] + 1;
       const int64_t ncol = (bx.hi[0] - bx.lo[0] + 1) * nj;
@@ -504,7 +534,9 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
         int32_t b = 0, e = 0;
         if (c < ncol) {
           const int64_t ci = bx.lo[0] + c / nj, cj = bx.lo[1] + c % nj;
-          if (column_near(g, tb, ci, cj, pad)) column_run<FL>(A.vx, g, ci, cj, bx.lo[2], bx.hi[2], &b, &e);
+          // the cube's box already bounds every column it holds
+          if (KS == kCube || column_near(g, tb, ci, cj, pad))
+            column_run<FL>(A.vx, g, ci, cj, bx.lo[2], bx.hi[2], &b, &e);
         }
         uint64_t m = __ballot(e > b);
         while (m) {
@@ -520,9 +552,7 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
 #pragma unroll 4
             for (int32_t p = rb; p < re; ++p) {
               const float4 P = load_const(cp, p);
-              const float dx = q.x - P.x, dy = q.y - P.y, dz = q.z - P.z;
-              const float D = (dx * dx + dy * dy) + dz * dz;
-              cnt += D <= R ? 1 : 0;
+              cnt += inside<KS>(q, P, rr, R) ? 1 : 0;
             }
           } else {
             // groups of kGroup candidates: their loads are issued together,
@@ -539,19 +569,15 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
               for (int u = 0; u < kGroup; ++u) P[u] = load_const(cp, p + u);
 #pragma unroll
               for (int u = 0; u < kGroup; ++u) {
-                const float dx = q.x - P[u].x, dy = q.y - P[u].y, dz = q.z - P[u].z;
-                const float D = (dx * dx + dy * dy) + dz * dz;
                 my_seg[nb] = __float_as_int(P[u].w) - poff;
-                nb += D <= R ? 1 : 0;
+                nb += inside<KS>(q, P[u], rr, R) ? 1 : 0;
               }
               if (__ballot(nb > kStage - kGroup)) flush_stage<false>(seg_base, rows, lane, nb, wpos, wend, A.nbr);
             }
             for (; p < re; ++p) {
               const float4 P = load_const(cp, p);
-              const float dx = q.x - P.x, dy = q.y - P.y, dz = q.z - P.z;
-              const float D = (dx * dx + dy * dy) + dz * dz;
               my_seg[nb] = __float_as_int(P.w) - poff;
-              nb += D <= R ? 1 : 0;
+              nb += inside<KS>(q, P, rr, R) ? 1 : 0;
               if (__ballot(nb > kStage - kGroup)) flush_stage<false>(seg_base, rows, lane, nb, wpos, wend, A.nbr);
             }
           }
@@ -565,7 +591,7 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
 
 // MULTI: per-item tile lookups and, if a counter is given, a persistent
 // loop over work items; otherwise one wave per item with tile 0's grid.
-template <bool FILL, bool MULTI, int FL>
+template <bool FILL, bool MULTI, int FL, int KS>
 __global__ __launch_bounds__(kThreads) void k_radius(RadiusArgs A) {
   __shared__ int32_t s_stage[FILL ? kWavesPerBlock * kWave * kStageStride : 1];
   __shared__ RowSlot s_rows[FILL ? kWavesPerBlock * kWave : 1];
@@ -574,13 +600,13 @@ __global__ __launch_bounds__(kThreads) void k_radius(RadiusArgs A) {
   RowSlot* rows = s_rows + (FILL ? w * kWave : 0);
   int64_t own = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
   if (!MULTI) {
-    if (own < A.W.nwaves) radius_item<FILL, false, FL>(A, item_of(A.W, own), lane, seg_base, rows);
+    if (own < A.W.nwaves) radius_item<FILL, false, FL, KS>(A, item_of(A.W, own), lane, seg_base, rows);
     return;
   }
   while (true) {
     const int64_t item = next_item(A.W, &own, lane);
     if (item >= A.W.nwaves) break;
-    radius_item<FILL, true, FL>(A, item_of(A.W, item), lane, seg_base, rows);
+    radius_item<FILL, true, FL, KS>(A, item_of(A.W, item), lane, seg_base, rows);
   }
 }
 
@@ -707,7 +733,7 @@ __device__ __forceinline__ void merge_buffer(uint64_t (&best)[KC], const uint64_
   nb = 0;
 }
 
-// Scan the candidates [rb, re) of one run (wave-uniform), groups of kGroup
+// Scan the candidates [rb, re) of one run (wave-uniform), groups of KnnBuf::group
 // loaded together through the scalar unit.
 template <int KC>
 __device__ __forceinline__ void knn_scan(const_pts cp, int32_t rb, int32_t re, float4 q,
@@ -967,23 +993,31 @@ static chs_status launch_dims(chs_index ix, const QueryPlan& plan, hipStream_t s
   return CHS_OK;
 }
 
-// kernel instance for the index's flavor and launch mode
-template <bool FILL>
-static void launch_radius(chs_index ix, unsigned nb, hipStream_t st, const RadiusArgs& A) {
+// kernel instance for the index's flavor, launch mode and search kernel
+template <bool FILL, int KS>
+static void launch_radius_ks(chs_index ix, unsigned nb, hipStream_t st, const RadiusArgs& A) {
   const bool mt = multi(ix);
   switch (ix->flavor) {
     case CHS_DENSE:
-      mt ? k_radius<FILL, true, CHS_DENSE><<<nb, kThreads, 0, st>>>(A)
-         : k_radius<FILL, false, CHS_DENSE><<<nb, kThreads, 0, st>>>(A);
+      mt ? k_radius<FILL, true, CHS_DENSE, KS><<<nb, kThreads, 0, st>>>(A)
+         : k_radius<FILL, false, CHS_DENSE, KS><<<nb, kThreads, 0, st>>>(A);
       break;
     case CHS_SPARSE:
-      mt ? k_radius<FILL, true, CHS_SPARSE><<<nb, kThreads, 0, st>>>(A)
-         : k_radius<FILL, false, CHS_SPARSE><<<nb, kThreads, 0, st>>>(A);
+      mt ? k_radius<FILL, true, CHS_SPARSE, KS><<<nb, kThreads, 0, st>>>(A)
+         : k_radius<FILL, false, CHS_SPARSE, KS><<<nb, kThreads, 0, st>>>(A);
       break;
     default:
-      mt ? k_radius<FILL, true, CHS_MIXED><<<nb, kThreads, 0, st>>>(A)
-         : k_radius<FILL, false, CHS_MIXED><<<nb, kThreads, 0, st>>>(A);
+      mt ? k_radius<FILL, true, CHS_MIXED, KS><<<nb, kThreads, 0, st>>>(A)
+         : k_radius<FILL, false, CHS_MIXED, KS><<<nb, kThreads, 0, st>>>(A);
   }
+}
+
+template <bool FILL>
+static void launch_radius(chs_index ix, unsigned nb, hipStream_t st, const RadiusArgs& A,
+                          int32_t kernel) {
+  if (kernel == CHS_KERNEL_CUBE) launch_radius_ks<FILL, kCube>(ix, nb, st, A);
+  else if (kernel == CHS_KERNEL_CYLINDER) launch_radius_ks<FILL, kCylinder>(ix, nb, st, A);
+  else launch_radius_ks<FILL, kSphere>(ix, nb, st, A);
 }
 
 template <int KC>
@@ -1004,8 +1038,8 @@ static void launch_knn(chs_index ix, unsigned nb, hipStream_t st, const KnnArgs&
   }
 }
 
-static chs_status radius_count_impl(chs_index ix, const QueryPlan& plan, float r, int64_t* offsets,
-                                    hipStream_t st) {
+static chs_status radius_count_impl(chs_index ix, const QueryPlan& plan, int32_t kernel, float r,
+                                    int64_t* offsets, hipStream_t st) {
   Alloc al = ix->al;
   al.stream = st;
   const int64_t nq = plan.nq;
@@ -1017,14 +1051,14 @@ static chs_status radius_count_impl(chs_index ix, const QueryPlan& plan, float r
     CHS_TRY(launch_dims(ix, plan, st, &ctr, &nb));
     RadiusArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), r,
                  counts.as<int32_t>(), nullptr, nullptr};
-    launch_radius<false>(ix, nb, st, A);
+    launch_radius<false>(ix, nb, st, A, kernel);
     CHS_LAUNCH_CHECK();
   }
   CHS_TRY(exclusive_scan_i32_i64(al, counts.as<int32_t>(), offsets, nq));
   return CHS_OK;
 }
 
-static chs_status radius_fill_impl(chs_index ix, const QueryPlan& plan, float r,
+static chs_status radius_fill_impl(chs_index ix, const QueryPlan& plan, int32_t kernel, float r,
                                    const int64_t* offsets, int32_t* nbr, hipStream_t st) {
   if (plan.nq == 0) return CHS_OK;
   int32_t* ctr;
@@ -1032,7 +1066,7 @@ static chs_status radius_fill_impl(chs_index ix, const QueryPlan& plan, float r,
   CHS_TRY(launch_dims(ix, plan, st, &ctr, &nb));
   RadiusArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), r, nullptr,
                offsets, nbr};
-  launch_radius<true>(ix, nb, st, A);
+  launch_radius<true>(ix, nb, st, A, kernel);
   CHS_LAUNCH_CHECK();
   return CHS_OK;
 }
@@ -1045,14 +1079,23 @@ static chs_status check_r(float r) {
   return CHS_OK;
 }
 
+static chs_status check_kernel(int32_t kernel) {
+  if (kernel != CHS_KERNEL_SPHERE && kernel != CHS_KERNEL_CUBE && kernel != CHS_KERNEL_CYLINDER) {
+    set_error("unknown search kernel %d", kernel);
+    return CHS_E_INVALID;
+  }
+  return CHS_OK;
+}
+
 }  // namespace chs
 
 using namespace chs;
 
-extern "C" chs_status chs_radius_count(chs_index ix, const chs_queries* qs, float r,
-                                       int64_t* offsets, int64_t* total, hipStream_t st) {
+extern "C" chs_status chs_kernel_count(chs_index ix, const chs_queries* qs, int32_t kernel,
+                                       float r, int64_t* offsets, int64_t* total, hipStream_t st) {
   clear_error();
   CHS_TRY(check_queries(ix, qs));
+  CHS_TRY(check_kernel(kernel));
   CHS_TRY(check_r(r));
   if (!offsets || !total) {
     set_error("offsets or total is NULL");
@@ -1062,7 +1105,7 @@ extern "C" chs_status chs_radius_count(chs_index ix, const chs_queries* qs, floa
   al.stream = st;
   QueryPlan plan(&al);
   CHS_TRY(plan_queries(ix, qs, &plan, st));
-  CHS_TRY(radius_count_impl(ix, plan, r, offsets, st));
+  CHS_TRY(radius_count_impl(ix, plan, kernel, r, offsets, st));
   int64_t tot = 0;
   CHS_HIP(hipMemcpyAsync(&tot, offsets + qs->nq, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   CHS_HIP(hipStreamSynchronize(st));
@@ -1070,11 +1113,12 @@ extern "C" chs_status chs_radius_count(chs_index ix, const chs_queries* qs, floa
   return CHS_OK;
 }
 
-extern "C" chs_status chs_radius_fill(chs_index ix, const chs_queries* qs, float r,
-                                      const int64_t* offsets, int32_t* nbr, int64_t total,
+extern "C" chs_status chs_kernel_fill(chs_index ix, const chs_queries* qs, int32_t kernel,
+                                      float r, const int64_t* offsets, int32_t* nbr, int64_t total,
                                       hipStream_t st) {
   clear_error();
   CHS_TRY(check_queries(ix, qs));
+  CHS_TRY(check_kernel(kernel));
   CHS_TRY(check_r(r));
   if (!offsets || (total > 0 && !nbr) || total < 0) {
     set_error("offsets or nbr is NULL, or total < 0");
@@ -1084,15 +1128,16 @@ extern "C" chs_status chs_radius_fill(chs_index ix, const chs_queries* qs, float
   al.stream = st;
   QueryPlan plan(&al);
   CHS_TRY(plan_queries(ix, qs, &plan, st));
-  CHS_TRY(radius_fill_impl(ix, plan, r, offsets, nbr, st));
+  CHS_TRY(radius_fill_impl(ix, plan, kernel, r, offsets, nbr, st));
   return CHS_OK;
 }
 
-extern "C" chs_status chs_radius_search(chs_index ix, const chs_queries* qs, float r,
-                                        const chs_allocator* alloc, int64_t* offsets,
+extern "C" chs_status chs_kernel_search(chs_index ix, const chs_queries* qs, int32_t kernel,
+                                        float r, const chs_allocator* alloc, int64_t* offsets,
                                         int32_t** nbr, int64_t* total, hipStream_t st) {
   clear_error();
   CHS_TRY(check_queries(ix, qs));
+  CHS_TRY(check_kernel(kernel));
   CHS_TRY(check_r(r));
   if (!offsets || !nbr || !total) {
     set_error("offsets, nbr or total is NULL");
@@ -1111,7 +1156,7 @@ extern "C" chs_status chs_radius_search(chs_index ix, const chs_queries* qs, flo
   }
   QueryPlan plan(&al);
   CHS_TRY(plan_queries(ix, qs, &plan, st));
-  CHS_TRY(radius_count_impl(ix, plan, r, offsets, st));
+  CHS_TRY(radius_count_impl(ix, plan, kernel, r, offsets, st));
   int64_t tot = 0;
   CHS_HIP(hipMemcpyAsync(&tot, offsets + qs->nq, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   CHS_HIP(hipStreamSynchronize(st));
@@ -1122,7 +1167,7 @@ extern "C" chs_status chs_radius_search(chs_index ix, const chs_queries* qs, flo
       set_error("allocator returned NULL for %lld neighbour indices", (long long)tot);
       return CHS_E_NOMEM;
     }
-    chs_status s = radius_fill_impl(ix, plan, r, offsets, out, st);
+    chs_status s = radius_fill_impl(ix, plan, kernel, r, offsets, out, st);
     if (s != CHS_OK) {
       out_al.put(out);
       return s;
@@ -1131,6 +1176,24 @@ extern "C" chs_status chs_radius_search(chs_index ix, const chs_queries* qs, flo
   *nbr = out;
   *total = tot;
   return CHS_OK;
+}
+
+// The sphere entry points of Alg. 1 (Section 3.4.1).
+extern "C" chs_status chs_radius_count(chs_index ix, const chs_queries* qs, float r,
+                                       int64_t* offsets, int64_t* total, hipStream_t st) {
+  return chs_kernel_count(ix, qs, CHS_KERNEL_SPHERE, r, offsets, total, st);
+}
+
+extern "C" chs_status chs_radius_fill(chs_index ix, const chs_queries* qs, float r,
+                                      const int64_t* offsets, int32_t* nbr, int64_t total,
+                                      hipStream_t st) {
+  return chs_kernel_fill(ix, qs, CHS_KERNEL_SPHERE, r, offsets, nbr, total, st);
+}
+
+extern "C" chs_status chs_radius_search(chs_index ix, const chs_queries* qs, float r,
+                                        const chs_allocator* alloc, int64_t* offsets,
+                                        int32_t** nbr, int64_t* total, hipStream_t st) {
+  return chs_kernel_search(ix, qs, CHS_KERNEL_SPHERE, r, alloc, offsets, nbr, total, st);
 }
 
 extern "C" chs_status chs_knn(chs_index ix, const chs_queries* qs, int32_t k, float r_max,

@@ -176,31 +176,37 @@ class GridIndex:
         return {k: (None if v is None else v.clone()) for k, v in out.items()}
 
     # ---- fixed-radius search (Alg. 1)
-    def radius_count(self, r, queries=None, stream=None):
+    KERNELS = {"sphere": 0, "cube": 1, "cylinder": 2}
+
+    def radius_count(self, r, queries=None, stream=None, kernel="sphere"):
+        """Row offsets (int64 [nq+1]) and total of a kernel search; kernel is
+        "sphere", "cube" (half side r) or "cylinder" (radius r, any z)."""
         q, nq, keep = _queries(queries, self.n)
         off = torch.empty(nq + 1, dtype=torch.int64, device=self.device)
         tot = ctypes.c_int64(0)
         with torch.cuda.device(self.device):
-            check(lib().chs_radius_count(self._h, ctypes.byref(q), ctypes.c_float(r),
-                                         off.data_ptr(), ctypes.byref(tot), _stream(stream)),
-                  "chs_radius_count")
+            check(lib().chs_kernel_count(self._h, ctypes.byref(q), self.KERNELS[kernel],
+                                         ctypes.c_float(r), off.data_ptr(), ctypes.byref(tot),
+                                         _stream(stream)), "chs_kernel_count")
         return off, tot.value
 
-    def radius_fill(self, r, offsets, total, queries=None, out=None, stream=None):
+    def radius_fill(self, r, offsets, total, queries=None, out=None, stream=None, kernel="sphere"):
         q, nq, keep = _queries(queries, self.n)
         nbr = out if out is not None else torch.empty(max(total, 0), dtype=torch.int32,
                                                       device=self.device)
         with torch.cuda.device(self.device):
-            check(lib().chs_radius_fill(self._h, ctypes.byref(q), ctypes.c_float(r),
-                                        offsets.data_ptr(), nbr.data_ptr() if total else None,
-                                        total, _stream(stream)), "chs_radius_fill")
+            check(lib().chs_kernel_fill(self._h, ctypes.byref(q), self.KERNELS[kernel],
+                                        ctypes.c_float(r), offsets.data_ptr(),
+                                        nbr.data_ptr() if total else None, total,
+                                        _stream(stream)), "chs_kernel_fill")
         return nbr
 
-    def radius(self, r, queries=None, stream=None):
+    def radius(self, r, queries=None, stream=None, kernel="sphere"):
         """CSR neighbour lists: (offsets int64 [nq+1], nbr int32 [total]) of
-        original point indices with D <= fl32(r*r)."""
-        off, tot = self.radius_count(r, queries, stream)
-        nbr = self.radius_fill(r, off, tot, queries, stream=stream)
+        original point indices inside the kernel around each query (the
+        sphere: D <= fl32(r*r))."""
+        off, tot = self.radius_count(r, queries, stream, kernel)
+        nbr = self.radius_fill(r, off, tot, queries, stream=stream, kernel=kernel)
         return off, nbr
 
     # ---- k-NN (Section 3.4.2)

@@ -73,6 +73,25 @@ def test_batch_matches_oracle_per_tile(flavor):
         np.testing.assert_array_equal(d2[a:b], od)
 
 
+@pytest.mark.parametrize("kernel", ["cube", "cylinder"])
+def test_batch_other_kernels_match_oracle(kernel):
+    dev = _dev()
+    tiles, dens = _tiles(ntiles=10, seed=6, hi=15_000)
+    cells = [1.0] * len(tiles)
+    ix, toff = _batch(tiles, cells, "sparse", dev)
+    off, nbr = ix.radius(1.2, kernel=kernel)
+    off = off.cpu().numpy(); nbr = nbr.cpu().numpy()
+    for t, tile in enumerate(tiles):
+        ox = oracle.OracleIndex(tile, cells[t], flavor="sparse")
+        oo, on = ox.radius(1.2, nthreads=8, kernel=kernel)
+        a, b = toff[t], toff[t + 1]
+        o2 = off[a:b + 1] - off[a]
+        np.testing.assert_array_equal(o2, oo)
+        g = _csr_sorted(o2, nbr[off[a]:off[b]])
+        w = _csr_sorted(oo, on)
+        np.testing.assert_array_equal(g[1], w[1])
+
+
 def test_batch_launch_modes_and_per_tile_indexes_agree():
     from paper_2502_11602_amd import GridIndex
     dev = _dev()

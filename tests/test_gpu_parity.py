@@ -187,6 +187,60 @@ def test_radius_edge_cases():
     assert torch.equal(o1, o2) and torch.equal(n1, n2)
 
 
+@pytest.mark.parametrize("kernel", ["cube", "cylinder"])
+@pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
+def test_other_kernels_config0(kernel, flavor):
+    """Cube and cylinder kernels of Alg. 1 on config 0: point queries at
+    r = 0.5 and 1.5 m, coordinate queries (some far above the cloud)."""
+    dev = _dev()
+    c = cloudgen.config0()
+    gi = _gi()(torch.from_numpy(c["xyz"]).to(dev), cell=c["cell"], flavor=flavor)
+    ox = oracle.OracleIndex(c["xyz"], c["cell"], flavor=flavor)
+    q = c["queries"]
+    for r in (0.5, 1.5):
+        off, nbr = gi.radius(r, torch.from_numpy(q).to(dev), kernel=kernel)
+        ooff, onbr = ox.radius(r, pidx=q, nthreads=8, kernel=kernel)
+        _assert_csr_equal(off, nbr, ooff, onbr)
+    rng = np.random.default_rng(21)
+    qa = c["xyz"][rng.choice(len(c["xyz"]), 3000, replace=False)].copy()
+    qa[::3, 2] += 40.0
+    off, nbr = gi.radius(1.0, torch.from_numpy(qa).to(dev), kernel=kernel)
+    ooff, onbr = ox.radius(1.0, qxyz=qa, nthreads=8, kernel=kernel)
+    _assert_csr_equal(off, nbr, ooff, onbr)
+
+
+@pytest.mark.parametrize("kernel", ["cube", "cylinder"])
+@pytest.mark.parametrize("name", sorted(CLOUDS))
+@pytest.mark.parametrize("dims,s", [(3, 0.3), (2, 2.5)])
+def test_other_kernels_all_points(kernel, name, dims, s):
+    dev = _dev()
+    xyz = CLOUDS[name](4)
+    for flavor in ("dense", "sparse", "mixed"):
+        gi = _gi()(torch.from_numpy(xyz).to(dev), cell=s, dims=dims, flavor=flavor)
+        ox = oracle.OracleIndex(xyz, s, dims=dims, flavor=flavor)
+        r = 0.7 if name != "blob" else 0.05
+        off, nbr = gi.radius(r, kernel=kernel)
+        ooff, onbr = ox.radius(r, nthreads=8, kernel=kernel)
+        _assert_csr_equal(off, nbr, ooff, onbr)
+
+
+def test_radius_rejects_bad_kernel():
+    import ctypes
+    from paper_2502_11602_amd._lib import Queries, lib
+    dev = _dev()
+    gi = _gi()(torch.from_numpy(_walls(2)).to(dev), cell=0.5)
+    q = Queries(None, None, gi.n)
+    tot = ctypes.c_int64(0)
+    off = torch.empty(gi.n + 1, dtype=torch.int64, device=dev)
+    call = lambda kern: lib().chs_kernel_count(gi._h, ctypes.byref(q), kern,  # noqa: E731
+                                               ctypes.c_float(1.0), off.data_ptr(),
+                                               ctypes.byref(tot), None)
+    assert call(1) == 0 and tot.value > 0
+    assert call(7) == 1 and b"kernel" in lib().chs_last_error()
+    with pytest.raises(KeyError):
+        gi.radius(1.0, kernel="torus")
+
+
 def test_radius_rejects_bad_radius():
     from paper_2502_11602_amd import ChsError
     dev = _dev()
