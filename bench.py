@@ -335,6 +335,69 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def run_sweep(args):
+    """The paper's cell-size study on the 10 M-point ALS tile (Sections 5.1-5.2):
+    voxel edges 1, 2.5, 5, 7.5, 10 m x 2D/3D grids x dense/sparse/mixed
+    maps.  Per configuration: build time, device bytes per point (the
+    paper's minimum is one 8-byte pointer per point), radius search (count +
+    fill) at 1 and 3 m and k-NN at k = 16 over every point, one warm and one
+    measured pass each."""
+    import torch
+
+    import cloudgen
+    from paper_2502_11602_amd import GridIndex
+
+    print(f"[bench] generating ALS tile: {args.points} points", file=sys.stderr, flush=True)
+    xyz = cloudgen.config1(n=args.points)["xyz"]
+    n = xyz.shape[0]
+    x = torch.from_numpy(xyz).to(torch.device("cuda:0"))
+    torch.cuda.synchronize()
+    E = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    rows = []
+    for cell in (1.0, 2.5, 5.0, 7.5, 10.0):
+        for dims in (3, 2):
+            for fl in ("dense", "sparse", "mixed"):
+                rec = {}
+                for rep in range(2):
+                    ev = [E() for _ in range(5)]
+                    ev[0].record()
+                    ix = GridIndex(x, cell=cell, dims=dims, flavor=fl)
+                    ev[1].record()
+                    torch.cuda.synchronize()
+                    built = ix.info()["device_bytes"]
+                    off, nbr = ix.radius(1.0)
+                    ev[2].record()
+                    del off, nbr
+                    off, nbr = ix.radius(3.0)
+                    ev[3].record()
+                    del off, nbr
+                    idx, d2 = ix.knn(16)
+                    ev[4].record()
+                    del idx, d2
+                    torch.cuda.synchronize()
+                    rec = {"cell_m": cell, "dims": dims, "flavor": fl,
+                           "build_ms": ev[0].elapsed_time(ev[1]),
+                           "radius_1m_ms": ev[1].elapsed_time(ev[2]),
+                           "radius_3m_ms": ev[2].elapsed_time(ev[3]),
+                           "knn16_ms": ev[3].elapsed_time(ev[4]),
+                           "device_bytes_per_point": built / n,
+                           "nonempty_voxels": ix.info()["n_nonempty"]}
+                    ix.close()
+                rows.append(rec)
+                print(f"[bench] sweep cell={cell} dims={dims} {fl} done", file=sys.stderr, flush=True)
+    best = min(rows, key=lambda r: r["radius_1m_ms"] + r["radius_3m_ms"] + r["knn16_ms"])
+    ms = best["build_ms"] + best["radius_1m_ms"] + best["radius_3m_ms"] + best["knn16_ms"]
+    out = {"metric": "cell-size x 2D/3D x flavor sweep: best queries/s (build + r=1,3 m + k=16)",
+           "value": 3 * n / (ms / 1e3), "unit": "queries/s", "n_gpus": 1, "steps": 1,
+           "warmup": 1, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"ALS tile, {n} points, every point a query; voxel edges "
+                                  "1-10 m, 2D and 3D grids, dense/sparse/mixed maps",
+                      "n_points": n},
+           "paper_min_bytes_per_point": 8, "best": best, "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -352,7 +415,7 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size before the steps "
                          "(a known-size kernel for scaling hardware byte counters)")
-    ap.add_argument("--workload", default="als10m", choices=["als10m", "batched"])
+    ap.add_argument("--workload", default="als10m", choices=["als10m", "batched", "sweep"])
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--batch-r", type=float, default=1.0)
     ap.add_argument("--batch-k", type=int, default=16)
@@ -373,6 +436,9 @@ def main():
 
     if args.workload == "batched":
         run_batched(args)
+        return
+    if args.workload == "sweep":
+        run_sweep(args)
         return
 
     import numpy as np
