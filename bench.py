@@ -12,7 +12,8 @@ timed region; each call's results are produced in full (CSR neighbour lists,
 Prints one JSON line.  ``value`` is queries answered per second over the
 whole step (7 query batches of N queries, index build included).  After the
 timed steps, one step per voxel map (dense, sparse, mixed) is reported as
-the flavor comparison, and the cube and cylinder kernels per radius.
+the flavor comparison, then the cube and cylinder kernels per radius and
+k-NN with Alg. 2's density-growth schedule.
 """
 import argparse
 import hashlib
@@ -561,6 +562,19 @@ def main():
     shapes = {}
     if not args.no_kernel_compare:
         ix = GridIndex(x, cell=args.cell, flavor=args.flavor)
+        # Alg. 2's density-growth schedule for k-NN (same lists as the rings)
+        ix.set_knn_schedule("density")
+        shapes["knn_density_schedule"] = {}
+        for k in ks:
+            for rep in range(2):
+                a, b = E(), E()
+                a.record()
+                idx, d2 = ix.knn(k)
+                b.record()
+                torch.cuda.synchronize()
+            shapes["knn_density_schedule"][str(k)] = {"ms": a.elapsed_time(b)}
+            del idx, d2
+        ix.set_knn_schedule("rings")
         for kern in ("cube", "cylinder"):
             shapes[kern] = {}
             for r in radii:

@@ -144,8 +144,15 @@ chs_status chs_tile_info(chs_index index, int32_t tile, chs_index_info_t* out /*
 /* CHS_OPT_PERSISTENT (default: on for batched indexes, off otherwise):
  * searches launch one wave per hardware slot and the waves pull 64-query
  * work items (largest tiles first) from a device counter until none is left,
- * instead of one wave per work item.  Results are identical either way. */
-typedef enum chs_option { CHS_OPT_PERSISTENT = 1 } chs_option;
+ * instead of one wave per work item.  Results are identical either way.
+ * CHS_OPT_KNN_SCHEDULE (default 0): how chs_knn grows the visited voxels.
+ * 0 = rings: one voxel per step, a query is done once its k-th distance is
+ * below the distance to the visited box's faces.  1 = density growth, the
+ * schedule of Alg. 2 (Section 3.4.2): the radius starts at the distance to
+ * the nearest wall of the query's voxel (Eq. 11) and grows from the density
+ * of the candidates within it (Eq. 12), a query being done once k of them
+ * lie within the radius.  Results are identical; only the cost differs. */
+typedef enum chs_option { CHS_OPT_PERSISTENT = 1, CHS_OPT_KNN_SCHEDULE = 4 } chs_option;
 chs_status chs_index_set_option(chs_index index, int32_t option, int64_t value);
 
 /* Device arrays of a built index, borrowed (valid until chs_free, never to

@@ -113,6 +113,7 @@ struct chs_index_s {
   int64_t device_bytes = 0;
   int64_t max_dense = (int64_t)INT32_MAX - 1;
   bool persistent = false;  // searches pull waves from a work counter
+  bool knn_density = false;  // k-NN with the density-growth schedule of Alg. 2
   // per tile, host copies (tile 0 is the whole cloud of a plain index)
   std::vector<chs::Grid> tiles;
   std::vector<double> origin;   // [3 * ntiles]

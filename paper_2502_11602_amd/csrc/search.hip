@@ -784,7 +784,42 @@ __device__ __forceinline__ void knn_scan(const_pts cp, int32_t rb, int32_t re, f
   }
 }
 
-template <int KC, bool MULTI, int FL>
+// Box of voxels (clamped into the grid) covering the padded balls of radius
+// r around the queries of the unfinished lanes, as a hull with V when V is
+// not empty (uniform).
+__device__ __forceinline__ IBox lane_hull(const Grid& g, const float (&qc)[3], double r, bool live,
+                                          const IBox& V, bool vempty) {
+  IBox B;
+  const double pad = fmax(r * (1.0 + kPadRel), kPadAbs);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a >= g.dims) {
+      B.lo[a] = B.hi[a] = 0;
+      continue;
+    }
+    const int32_t lo = (int32_t)voxel_clamped((double)qc[a] - pad, g.s[a], g.n[a]);
+    const int32_t hi = (int32_t)voxel_clamped((double)qc[a] + pad, g.s[a], g.n[a]);
+    int32_t l = wave_min(live ? lo : INT32_MAX), h = wave_max(live ? hi : INT32_MIN);
+    if (!vempty) {
+      l = V.lo[a] < l ? V.lo[a] : l;
+      h = V.hi[a] > h ? V.hi[a] : h;
+    }
+    B.lo[a] = l;
+    B.hi[a] = h;
+  }
+  return B;
+}
+
+// SCHED: kRings grows the visited box by one voxel per step and stops a
+// lane by the distance to the box's faces; kDensity is the schedule of
+// Alg. 2: each lane starts at the distance to the nearest wall of its voxel
+// (Eq. 11), grows its radius from the density of the candidates within it
+// (Eq. 12) or by the smallest voxel edge, and stops once k keys lie within
+// the radius.  The wave visits the hull of its unfinished lanes' kernel
+// boxes.  Both give the exact k nearest.
+constexpr int kRings = 0, kDensity = 1;
+
+template <int KC, bool MULTI, int FL, int SCHED>
 __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int lane,
                                          uint64_t* seg) {
   const Grid g = MULTI ? A.W.tiles[it.tile] : A.g0;
@@ -804,21 +839,42 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
   uint64_t kthk = ~0ull;
   int nb = 0;
   if (tb.any) {
-    // ring 0: the voxels holding the tile's queries (clamped into the grid);
-    // voxel coordinates fit 32 bits (fewer than 1e9 voxels per axis)
-    IBox B;
+    const float qc[3] = {q.x, q.y, q.z};
+    // density schedule: the lane's radius, starting at the distance from
+    // the query to the nearest wall of its voxel (Eq. 11)
+    double rL = 0.0, smin = INFINITY;
+    bool done = !active;
+    if (SCHED == kDensity) {
+      rL = INFINITY;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (a >= g.dims) {
-        B.lo[a] = B.hi[a] = 0;
-        continue;
+      for (int a = 0; a < 3; ++a) {
+        if (a >= g.dims) continue;
+        smin = fmin(smin, g.s[a]);
+        const double c = (double)qc[a];
+        const double v = (double)voxel_clamped(c, g.s[a], g.n[a]);
+        rL = fmin(rL, fmin(fabs(c - v * g.s[a]), fabs(c - (v + 1.0) * g.s[a])));
       }
-      B.lo[a] = first_lane((int32_t)voxel_clamped((double)tb.lo[a], g.s[a], g.n[a]));
-      B.hi[a] = first_lane((int32_t)voxel_clamped((double)tb.hi[a], g.s[a], g.n[a]));
+      if (!(rL > 0.0)) rL = smin;  // a centre on a wall would start at 0
     }
     IBox V;  // visited voxels (the taboo box)
     bool vempty = true;
-    const float qc[3] = {q.x, q.y, q.z};
+    // first box: the voxels holding the tile's queries (clamped into the
+    // grid), or the unfinished lanes' kernel boxes; voxel coordinates fit
+    // 32 bits (fewer than 1e9 voxels per axis)
+    IBox B;
+    if (SCHED == kDensity) {
+      B = lane_hull(g, qc, rL, !done, V, true);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (a >= g.dims) {
+          B.lo[a] = B.hi[a] = 0;
+          continue;
+        }
+        B.lo[a] = first_lane((int32_t)voxel_clamped((double)tb.lo[a], g.s[a], g.n[a]));
+        B.hi[a] = first_lane((int32_t)voxel_clamped((double)tb.hi[a], g.s[a], g.n[a]));
+      }
+    }
     // Points farther from the tile's query box than every unfinished lane's
     // threshold can never enter a list (thresholds only shrink), so columns
     // and z-ranges beyond that distance are skipped; +inf until every
@@ -827,7 +883,8 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
     while (true) {
       int32_t kz0 = B.lo[2], kz1 = B.hi[2];
       double padk = INFINITY;
-      if (tau < INFINITY) {
+      // (the density schedule's radii grow, so nothing may be skipped there)
+      if (SCHED == kRings && tau < INFINITY) {
         padk = fmax(sqrt(tau) * (1.0 + kPadRel), kPadAbs);
         if (g.dims == 3) {
           const double zlo = floor(((double)tb.lo[2] - padk) / g.s[2]);
@@ -878,6 +935,38 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
       kthk = kth_key<KC>(best, A.k);
       V = B;
       vempty = false;
+      bool whole = true;  // V is the whole grid (decided from V alone: uniform)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (a >= g.dims) continue;
+        if (V.lo[a] > 0 || V.hi[a] < g.n[a] - 1) whole = false;
+      }
+      if (whole) break;
+      if (SCHED == kDensity) {
+        // k keys within fl32(rL^2): every unvisited point lies beyond the
+        // padded ball of radius rL, so its D exceeds that bound; past the
+        // radius cap nothing more can be returned
+        const float T = (float)(rL * rL);
+        const uint32_t tb32 = __float_as_uint(T);
+        done = done || (kthk != ~0ull && (uint32_t)(kthk >> 32) <= tb32) ||
+               (double)A.rmax2 <= rL * rL;
+        if (__ballot(!done) == 0ull) break;
+        if (!done) {
+          // |P^|: candidates within the radius (Eq. 10); the list is sorted
+          int np = 0;
+#pragma unroll
+          for (int i = 0; i < KC; ++i) np += (uint32_t)(best[i] >> 32) <= tb32 ? 1 : 0;
+          double rn = rL + smin;  // monotonic growth
+          if (np > 0) {
+            const double rho = (double)np / ((4.0 / 3.0) * M_PI * rL * rL * rL);  // Eq. 12
+            const double rd = cbrt((double)A.k / rho);
+            if (rd > rL) rn = rd;
+          }
+          rL = rn;
+        }
+        B = lane_hull(g, qc, rL, !done, V, false);
+        continue;
+      }
       // termination: every point outside V lies beyond the nearest face of V
       // that is not on the grid boundary; once the k-th best (or the radius
       // cap) is strictly below that distance squared, nothing outside V can
@@ -888,7 +977,6 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
         thr = dk < thr ? dk : thr;
       }
       double lb = INFINITY;
-      bool whole = true;  // V is the whole grid (decided from V alone: uniform)
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         if (a >= g.dims) continue;
@@ -896,18 +984,15 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
         if (V.lo[a] > 0) {
           const double f = (double)V.lo[a] * g.s[a];
           lb = fmin(lb, (c - f) - 0x1p-50 * (fabs(c) + fabs(f)));
-          whole = false;
         }
         if (V.hi[a] < g.n[a] - 1) {
           const double f = (double)(V.hi[a] + 1) * g.s[a];
           lb = fmin(lb, (f - c) - 0x1p-50 * (fabs(c) + fabs(f)));
-          whole = false;
         }
       }
-      if (whole) break;
       lb = fmax(lb, 0.0);
       const double lb2 = lb * lb;
-      const bool done = !active || (lb2 >= 0x1p-100 && (double)thr < lb2 * (1.0 - kPadRel));
+      done = !active || (lb2 >= 0x1p-100 && (double)thr < lb2 * (1.0 - kPadRel));
       if (__ballot(!done) == 0ull) break;
       tau = wave_max(done ? -INFINITY : (double)thr);
       // next ring: grow the box by one voxel on every side
@@ -938,7 +1023,7 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
 // Lists of 32 run at four waves per SIMD, of 16 at six and of 8 at eight:
 // the few registers spilled cost less than the latency hiding gained
 // (measured on the 10 M-point tile).
-template <int KC, bool MULTI, int FL>
+template <int KC, bool MULTI, int FL, int SCHED>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KC == 32 ? 4 : (KC == 16 ? 6 : (KC == 8 ? 8 : 1)))))
 void k_knn(KnnArgs A) {
   constexpr int kSeg = KnnBuf<KC>::on ? kWave * KnnBuf<KC>::stride : 1;
@@ -947,13 +1032,13 @@ void k_knn(KnnArgs A) {
   uint64_t* seg = s_buf + w * kSeg + (KnnBuf<KC>::on ? lane * KnnBuf<KC>::stride : 0);
   int64_t own = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
   if (!MULTI) {
-    if (own < A.W.nwaves) knn_item<KC, false, FL>(A, item_of(A.W, own), lane, seg);
+    if (own < A.W.nwaves) knn_item<KC, false, FL, SCHED>(A, item_of(A.W, own), lane, seg);
     return;
   }
   while (true) {
     const int64_t item = next_item(A.W, &own, lane);
     if (item >= A.W.nwaves) break;
-    knn_item<KC, true, FL>(A, item_of(A.W, item), lane, seg);
+    knn_item<KC, true, FL, SCHED>(A, item_of(A.W, item), lane, seg);
   }
 }
 
@@ -1020,22 +1105,28 @@ static void launch_radius(chs_index ix, unsigned nb, hipStream_t st, const Radiu
   else launch_radius_ks<FILL, kSphere>(ix, nb, st, A);
 }
 
-template <int KC>
-static void launch_knn(chs_index ix, unsigned nb, hipStream_t st, const KnnArgs& A) {
+template <int KC, int SCHED>
+static void launch_knn_s(chs_index ix, unsigned nb, hipStream_t st, const KnnArgs& A) {
   const bool mt = multi(ix);
   switch (ix->flavor) {
     case CHS_DENSE:
-      mt ? k_knn<KC, true, CHS_DENSE><<<nb, kThreads, 0, st>>>(A)
-         : k_knn<KC, false, CHS_DENSE><<<nb, kThreads, 0, st>>>(A);
+      mt ? k_knn<KC, true, CHS_DENSE, SCHED><<<nb, kThreads, 0, st>>>(A)
+         : k_knn<KC, false, CHS_DENSE, SCHED><<<nb, kThreads, 0, st>>>(A);
       break;
     case CHS_SPARSE:
-      mt ? k_knn<KC, true, CHS_SPARSE><<<nb, kThreads, 0, st>>>(A)
-         : k_knn<KC, false, CHS_SPARSE><<<nb, kThreads, 0, st>>>(A);
+      mt ? k_knn<KC, true, CHS_SPARSE, SCHED><<<nb, kThreads, 0, st>>>(A)
+         : k_knn<KC, false, CHS_SPARSE, SCHED><<<nb, kThreads, 0, st>>>(A);
       break;
     default:
-      mt ? k_knn<KC, true, CHS_MIXED><<<nb, kThreads, 0, st>>>(A)
-         : k_knn<KC, false, CHS_MIXED><<<nb, kThreads, 0, st>>>(A);
+      mt ? k_knn<KC, true, CHS_MIXED, SCHED><<<nb, kThreads, 0, st>>>(A)
+         : k_knn<KC, false, CHS_MIXED, SCHED><<<nb, kThreads, 0, st>>>(A);
   }
+}
+
+template <int KC>
+static void launch_knn(chs_index ix, unsigned nb, hipStream_t st, const KnnArgs& A) {
+  if (ix->knn_density) launch_knn_s<KC, kDensity>(ix, nb, st, A);
+  else launch_knn_s<KC, kRings>(ix, nb, st, A);
 }
 
 static chs_status radius_count_impl(chs_index ix, const QueryPlan& plan, int32_t kernel, float r,

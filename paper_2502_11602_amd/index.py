@@ -129,6 +129,12 @@ class GridIndex:
         work items from a device counter (default for batched indexes)."""
         check(lib().chs_index_set_option(self._h, 1, 1 if on else 0), "chs_index_set_option")
 
+    def set_knn_schedule(self, schedule="rings"):
+        """k-NN voxel schedule: "rings" (default) or "density" (Alg. 2's
+        density-growth radius); the results are identical."""
+        check(lib().chs_index_set_option(self._h, 4, {"rings": 0, "density": 1}[schedule]),
+              "chs_index_set_option")
+
     def tile_info(self, t):
         inf = IndexInfo()
         check(lib().chs_tile_info(self._h, t, ctypes.byref(inf)), "chs_tile_info")

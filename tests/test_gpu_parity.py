@@ -295,6 +295,44 @@ def test_knn_coordinate_queries_and_rmax(flavor):
         np.testing.assert_array_equal(d2.cpu().numpy(), od)
 
 
+@pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
+def test_knn_density_schedule(flavor):
+    """Alg. 2's density-growth schedule (CHS_OPT_KNN_SCHEDULE = 1) returns
+    the oracle's lists and the ring schedule's, exactly: config 0 at
+    k = 1, 16, 40, coordinate queries with an r_max cap, the adversarial
+    clouds."""
+    dev = _dev()
+    c = cloudgen.config0()
+    gi = _gi()(torch.from_numpy(c["xyz"]).to(dev), cell=c["cell"], flavor=flavor)
+    ox = oracle.OracleIndex(c["xyz"], c["cell"], flavor=flavor)
+    q = torch.from_numpy(c["queries"]).to(dev)
+    for k in (1, 16, 40):
+        ir, dr = gi.knn(k, q)
+        gi.set_knn_schedule("density")
+        idx, d2 = gi.knn(k, q)
+        gi.set_knn_schedule("rings")
+        oi, od = ox.knn(k, pidx=c["queries"], nthreads=8)
+        np.testing.assert_array_equal(idx.cpu().numpy(), oi)
+        np.testing.assert_array_equal(d2.cpu().numpy(), od)
+        assert torch.equal(idx, ir) and torch.equal(d2, dr)
+    rng = np.random.default_rng(31)
+    qa = rng.uniform(c["xyz"].min(0) - 5.0, c["xyz"].max(0) + 5.0, (2000, 3))
+    gi.set_knn_schedule("density")
+    idx, d2 = gi.knn(12, torch.from_numpy(qa).to(dev), r_max=1.5)
+    oi, od = ox.knn(12, r_max=1.5, qxyz=qa, nthreads=8)
+    np.testing.assert_array_equal(idx.cpu().numpy(), oi)
+    np.testing.assert_array_equal(d2.cpu().numpy(), od)
+    for name in sorted(CLOUDS):
+        xyz = CLOUDS[name](4)
+        g2 = _gi()(torch.from_numpy(xyz).to(dev), cell=0.3, flavor=flavor)
+        g2.set_knn_schedule("density")
+        i2, d2 = g2.knn(20)
+        o2 = oracle.OracleIndex(xyz, 0.3, flavor=flavor)
+        oi, od = o2.knn(20, nthreads=8)
+        np.testing.assert_array_equal(i2.cpu().numpy(), oi)
+        np.testing.assert_array_equal(d2.cpu().numpy(), od)
+
+
 def test_knn_edge_cases():
     dev = _dev()
     GI = _gi()
