@@ -31,11 +31,21 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2502_11602_amd/csrc/search.hip", "paper_2502_11602_amd/csrc/common.h"]
 
 
+def code_text(src):
+    """Kernel source without // comments and with whitespace collapsed: the
+    part that decides the compiled code."""
+    import re
+
+    lines = [re.sub(r"//.*$", "", ln) for ln in src.split("\n")]
+    return " ".join(" ".join(lines).split())
+
+
 def source_hash():
+    """Hash of the kernel sources' code (comment edits keep it)."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
@@ -168,8 +178,9 @@ def profile_summary(stats_dir, fetch_dir, write_dir, radii=(0.5, 1.0, 2.0, 3.0),
           f"| read  | {ff[-1]:.0f} | {fill_read:.4g} |",
           f"| write | {fw[-1]:.0f} | {fill_write:.4g} |",
           f"| total | | {fill_read + fill_write:.4g} |", "",
-          "Kernel sources hash: `%s` (bench.py reports this traffic only while the "
-          "sources match)." % rec["source_hash"]]
+          "Kernel sources hash: `%s` (hash of the kernel sources with comments and "
+          "whitespace removed; bench.py reports this traffic only while the code "
+          "matches)." % rec["source_hash"]]
     with open(os.path.join(out_dir, "radius_fill_als10m_pmc.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
     print(json.dumps({"kernels": len(agg), "fill_r3_ms": per_r[radii[-1]],

@@ -1,6 +1,7 @@
-// Neighbour search on the GPU: fixed-radius (the kernel-based search of
-// Section 3.4.1, Alg. 1, with a spherical kernel) and k-NN (Section 3.4.2,
-// with the taboo box of Section 3.5 as a ring expansion over voxels).
+// Neighbour search on the GPU: the kernel-based search of Section 3.4.1
+// (Alg. 1) with a sphere, a cube or a cylinder, and k-NN (Section 3.4.2,
+// Alg. 2, with the taboo box of Section 3.5), either as a ring expansion
+// over voxels or with Alg. 2's density-growth radius.
 //
 // Work decomposition: a wavefront owns a tile of 64 consecutive queries in
 // a Hilbert order over the (i, j) voxel columns, so its queries are spatial
@@ -10,8 +11,9 @@
 // Eq. 7), so each column yields one run of candidate points.  The wave then
 // walks the runs with wave-uniform indices, so every candidate point is
 // fetched once per wave through the scalar unit and compared against the 64
-// queries held in the lanes: no per-lane gathers, no LDS, and the distance
-// arithmetic is the unfused FP32 definition.
+// queries held in the lanes (no per-lane gathers), with the unfused FP32
+// arithmetic of the definitions.  LDS holds only per-lane output: the fill's
+// staged matches and the k-NN's buffered keys.
 #include <algorithm>
 #include <cmath>
 
@@ -342,13 +344,13 @@ struct IBox {
   int32_t lo[3], hi[3];
 };
 
-// Voxel box covering [lo - pad, hi + pad] along every indexed axis, clamped
-// to the grid; empty when it misses the grid.
 // Search kernels of Alg. 1 (Section 3.4.1; the cube and the cylinder of
 // Section 2): each gives the box around the queries and an inside test.
 enum KernelShape { kSphere = 0, kCube = 1, kCylinder = 2 };
 
-// KS: the cylinder's box spans every z voxel
+// Voxel box covering [lo - pad, hi + pad] along every indexed axis, clamped
+// to the grid; empty when it misses the grid.  KS: the cylinder's box spans
+// every z voxel.
 template <int KS = kSphere>
 __device__ __forceinline__ VBox voxel_box(const Grid& g, const float* lo, const float* hi,
                                           double pad) {
