@@ -223,6 +223,110 @@ def cpu_baseline(xyz, radii, ks, cell, sample, nthreads):
     }
 
 
+def agg_bytes(N, Q, K, C, P, fbytes):
+    """Algorithmic HBM bytes of the aggregation passes for Q centres with K
+    slots each, P valid (centre, neighbour) pairs, C channels of fbytes bytes:
+    every pair reads its neighbour's feature row and coordinates once.
+    Forward: rows 4C and x 12 per pair, the lists 4KQ, centres 16Q, output.
+    Backward (the sort excluded): the pair pass reads the rows, x and g per
+    centre and writes w, s, key and value per slot and the centre gradient;
+    the point pass reads per pair the sorted slot, w, s, the centre index,
+    its coordinates and g row, and writes the feature and coordinate
+    gradients."""
+    row = C * fbytes
+    fwd = P * (row + 12) + 4 * K * Q + 16 * Q + row * Q
+    pairs = P * (row + 12) + row * Q + 4 * K * Q + 16 * K * Q + 8 * Q + 16 * Q
+    points = P * (4 + 8 + 4 + 12 + row) + 8 * (N + 1) + 4 * Q + N * (row + 12)
+    return fwd, pairs + points
+
+
+def run_agg(args):
+    """Aggregation workload: 1 M ALS-like points at about 50 points per
+    square metre, 64-channel N(0, 1) features, 250 k centres drawn from the
+    points, neighbour lists of the 64 nearest within 0.5 m, sigma 0.25 m.
+    Times the neighbour search, the forward and the backward with FP32 and
+    with BF16 features, and reports each pass's bandwidth for its
+    algorithmic bytes (agg_bytes) against the HBM peak."""
+    import numpy as np
+    import torch
+
+    import cloudgen
+    from paper_2502_11602_amd import GridIndex, gauss_aggregate, neighbour_lists
+    from paper_2502_11602_amd.agg import recentred
+
+    c = cloudgen.config4()
+    dev = torch.device("cuda:0")
+    x64 = torch.from_numpy(c["xyz"]).to(dev)
+    q = torch.from_numpy(c["queries"]).to(dev)
+    f32 = torch.from_numpy(c["f"]).to(dev)
+    N, C = f32.shape
+    Q, K, sigma = q.numel(), c["k"], c["sigma"]
+    E = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def timed(fn, reps):
+        ts = []
+        for _ in range(reps):
+            a, b = E(), E()
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return sum(ts[1:]) / max(1, len(ts) - 1)  # the first is a warm-up
+
+    reps = max(2, args.steps + 1)
+    ix = GridIndex(x64, cell=args.agg_cell, flavor="dense")
+    nbr = neighbour_lists(ix, q, k=K, r_max=c["r"])
+    t_nbr = timed(lambda: neighbour_lists(ix, q, k=K, r_max=c["r"]), reps)
+    x32 = recentred(x64, ix)
+    P = int((nbr >= 0).sum())
+    res = {}
+    for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+        f = f32.to(dt)
+        g = torch.randn((Q, C), generator=torch.Generator().manual_seed(3)).to(dev).to(dt)
+        with torch.no_grad():
+            t_fwd = timed(lambda: gauss_aggregate(x32, f, q, nbr, sigma=sigma), reps)
+        xg = x32.clone().requires_grad_(True)
+        fg = f.clone().requires_grad_(True)
+
+        def fwd_bwd():
+            xg.grad = None
+            fg.grad = None
+            out = gauss_aggregate(xg, fg, q, nbr, sigma=sigma)
+            out.backward(g)
+
+        t_fb = timed(fwd_bwd, reps)
+        t_bwd = t_fb - t_fwd
+        bf, bb = agg_bytes(N, Q, K, C, P, 2 if dt == torch.bfloat16 else 4)
+        res[name] = {"forward_ms": t_fwd, "backward_ms": t_bwd,
+                     "forward_gbs": bf / (t_fwd / 1e3) / 1e9,
+                     "backward_gbs": bb / (t_bwd / 1e3) / 1e9,
+                     "forward_bytes": bf, "backward_bytes": bb}
+        print(f"[bench] agg {name}: fwd {t_fwd:.3f} ms, bwd {t_bwd:.3f} ms",
+              file=sys.stderr, flush=True)
+    ix.close()
+    f = res["f32"]
+    out = {
+        "metric": "Gaussian aggregation: centres per sec (forward + backward, FP32 features)",
+        "value": Q / ((f["forward_ms"] + f["backward_ms"]) / 1e3),
+        "unit": "centres/s",
+        "n_gpus": 1, "steps": reps - 1, "warmup": 1,
+        "ms_per_step": f["forward_ms"] + f["backward_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"ALS-like cloud, {N} points at about 50 points/m^2, {Q} centres, "
+                               f"{C} channels, {K} nearest within {c['r']} m, sigma {sigma} m",
+                   "cell_m": args.agg_cell, "valid_pairs": P},
+        "neighbour_lists_ms": t_nbr,
+        "passes": res,
+        "roofline": {"kernel": "k_agg_fwd (f32)", "bound": "hbm",
+                     "achieved": f["forward_gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": f["forward_gbs"] / PEAK_HBM_GBS, "traffic": None,
+                     "algorithmic_bytes": f["forward_bytes"], "launch_ms": f["forward_ms"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_batched(args):
     """Batched workload: 256 ALS-like tiles, sizes log-uniform in 1e4..2e6
     (about 60 M points), densities 2-20 points per square metre; every point
@@ -427,7 +531,8 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size before the steps "
                          "(a known-size kernel for scaling hardware byte counters)")
-    ap.add_argument("--workload", default="als10m", choices=["als10m", "batched", "sweep"])
+    ap.add_argument("--workload", default="als10m", choices=["als10m", "batched", "sweep", "agg"])
+    ap.add_argument("--agg-cell", type=float, default=0.5)
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--batch-r", type=float, default=1.0)
     ap.add_argument("--batch-k", type=int, default=16)
@@ -451,6 +556,9 @@ def main():
         return
     if args.workload == "sweep":
         run_sweep(args)
+        return
+    if args.workload == "agg":
+        run_agg(args)
         return
 
     import numpy as np

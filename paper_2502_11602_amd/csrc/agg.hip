@@ -9,8 +9,11 @@
 // bitwise reproducible.
 //
 // Work layout: one wavefront per query (forward, backward pair pass) or per
-// point (backward point pass); the lanes hold channels, so every feature row
-// is read with one coalesced load per 64 channels.
+// point (backward point pass).  The lanes first take one list slot each and
+// gather its neighbour, coordinates and weight in parallel; then they hold
+// channels, and the wave walks the slots in order with the slot's values
+// broadcast, reading each feature row with one coalesced load per 64
+// channels, several rows in flight at a time.
 #include <cmath>
 
 #include "common.h"
@@ -67,6 +70,33 @@ __device__ __forceinline__ TA wave_sum(TA v) {
   return v;
 }
 
+// value of lane src (src uniform)
+__device__ __forceinline__ int32_t lane_get(int32_t v, int src) {
+  return __builtin_amdgcn_readlane(v, src);
+}
+__device__ __forceinline__ float lane_get(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double lane_get(double v, int src) {
+  const int64_t b = __double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)b, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)((uint64_t)b >> 32), src);
+  return __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
+}
+
+// slots walked per step: their feature rows are loaded together
+constexpr int kRows = 4;
+
+// the next up to kRows set bits of m (ascending), removed from m
+__device__ __forceinline__ void take_slots(uint64_t& m, int (&src)[kRows], bool (&ok)[kRows]) {
+#pragma unroll
+  for (int u = 0; u < kRows; ++u) {
+    ok[u] = m != 0;
+    src[u] = ok[u] ? __builtin_ctzll(m) : 0;
+    m &= m - 1;
+  }
+}
+
 template <class TX, class TA>
 __device__ __forceinline__ TA sqdist3(const TX* __restrict__ x, int64_t j, TA qx, TA qy, TA qz) {
   const TA dx = (TA)x[j * 3 + 0] - qx, dy = (TA)x[j * 3 + 1] - qy, dz = (TA)x[j * 3 + 2] - qz;
@@ -84,11 +114,12 @@ struct AggArgs {
 };
 
 // ---------------------------------------------------------------- forward
+// out[q, c] accumulates w * f[j, c] over the valid slots in slot order.
 template <class TX, class TF, class TA>
 __global__ __launch_bounds__(kThreads) void k_agg_fwd(AggArgs A, const TF* __restrict__ f,
                                                       TF* __restrict__ out) {
   const int lane = lane_id();
-  const int64_t q = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave;
+  const int64_t q = (int64_t)blockIdx.x * kWaves + first_lane((int32_t)(threadIdx.x / kWave));
   if (q >= A.Q) return;
   const TX* __restrict__ x = static_cast<const TX*>(A.x);
   const int64_t iq = A.qidx[q];
@@ -98,23 +129,48 @@ __global__ __launch_bounds__(kThreads) void k_agg_fwd(AggArgs A, const TF* __res
   const TA i2 = (TA)A.inv2s2;
   for (int c0 = 0; c0 < A.C; c0 += kWave) {
     const int c = c0 + lane;
+    const bool cin = c < A.C;
     TA acc = 0;
-    if (qok) {
-      for (int t = 0; t < A.K; ++t) {
-        const int64_t j = A.nbr[q * A.K + t];
-        if (j < 0 || j >= A.N) continue;
-        const TA w = gexp(-(sqdist3<TX, TA>(x, j, qx, qy, qz) * i2));
-        if (c < A.C) acc += w * load_f<TF, TA>(f, j * A.C + c);
+    for (int t0 = 0; qok && t0 < A.K; t0 += kWave) {
+      // lane l: slot t0 + l, its neighbour and weight
+      const int t = t0 + lane;
+      int32_t jl = -1;
+      TA wl = 0;
+      if (t < A.K) {
+        const int64_t jj = A.nbr[q * A.K + t];
+        if (jj >= 0 && jj < A.N) {
+          jl = (int32_t)jj;
+          wl = gexp(-(sqdist3<TX, TA>(x, jj, qx, qy, qz) * i2));
+        }
+      }
+      uint64_t m = __ballot(jl >= 0);
+      while (m) {
+        int src[kRows];
+        bool ok[kRows];
+        take_slots(m, src, ok);
+        // (broadcasts stay outside the per-lane channel test)
+        int32_t jv[kRows];
+        TA wv[kRows], fv[kRows];
+#pragma unroll
+        for (int u = 0; u < kRows; ++u) {
+          jv[u] = lane_get(jl, src[u]);
+          wv[u] = lane_get(wl, src[u]);
+          fv[u] = (ok[u] && cin) ? load_f<TF, TA>(f, (int64_t)jv[u] * A.C + c) : (TA)0;
+        }
+#pragma unroll
+        for (int u = 0; u < kRows; ++u)
+          if (ok[u] && cin) acc += wv[u] * fv[u];
       }
     }
-    if (c < A.C) store_f<TF, TA>(out, q * A.C + c, acc);
+    if (cin) store_f<TF, TA>(out, q * A.C + c, acc);
   }
 }
 
 // ---------------------------------------------------------------- backward
 // pass 1, one wave per query: per pair (q, t) the weight w and the scalar
 // s = (sum_c g[q,c] f[j,c]) w / sigma^2; the centre-role gradient
-// gq[q] = sum_t s (x_j - x_q); and the sort keys regrouping pairs by j.
+// gq[q] = sum_t s (x_j - x_q) in slot order; and the sort keys regrouping
+// pairs by j.
 template <class TX, class TF, class TA>
 __global__ __launch_bounds__(kThreads) void k_agg_bwd_pairs(AggArgs A, const TF* __restrict__ f,
                                                             const TF* __restrict__ g,
@@ -123,7 +179,7 @@ __global__ __launch_bounds__(kThreads) void k_agg_bwd_pairs(AggArgs A, const TF*
                                                             uint32_t* __restrict__ key,
                                                             uint32_t* __restrict__ val) {
   const int lane = lane_id();
-  const int64_t q = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave;
+  const int64_t q = (int64_t)blockIdx.x * kWaves + first_lane((int32_t)(threadIdx.x / kWave));
   if (q >= A.Q) return;
   const TX* __restrict__ x = static_cast<const TX*>(A.x);
   const int64_t iq = A.qidx[q];
@@ -131,31 +187,61 @@ __global__ __launch_bounds__(kThreads) void k_agg_bwd_pairs(AggArgs A, const TF*
   const TA qx = qok ? (TA)x[iq * 3] : (TA)0, qy = qok ? (TA)x[iq * 3 + 1] : (TA)0,
            qz = qok ? (TA)x[iq * 3 + 2] : (TA)0;
   const TA i2 = (TA)A.inv2s2, is2 = (TA)A.invs2;
+  // the gradient row of q for the first 64 channels stays in registers
+  const TA g0 = lane < A.C ? load_f<TF, TA>(g, q * A.C + lane) : (TA)0;
   TA cx = 0, cy = 0, cz = 0;
-  for (int t = 0; t < A.K; ++t) {
+  for (int t0 = 0; t0 < A.K; t0 += kWave) {
+    // lane l: slot t0 + l, its neighbour, offset and weight
+    const int t = t0 + lane;
     const int64_t p = q * A.K + t;
-    const int64_t j = A.nbr[p];
-    const bool ok = qok && j >= 0 && j < A.N;
-    TA w = 0, s = 0;
-    if (ok) {
-      const TA dx = (TA)x[j * 3 + 0] - qx, dy = (TA)x[j * 3 + 1] - qy, dz = (TA)x[j * 3 + 2] - qz;
-      w = gexp(-(((dx * dx + dy * dy) + dz * dz) * i2));
-      TA a = 0;
+    int32_t jl = -1;
+    TA wl = 0, dxl = 0, dyl = 0, dzl = 0, sl = 0;
+    if (t < A.K) {
+      const int64_t jj = A.nbr[p];
+      if (qok && jj >= 0 && jj < A.N) {
+        jl = (int32_t)jj;
+        dxl = (TA)x[jj * 3 + 0] - qx;
+        dyl = (TA)x[jj * 3 + 1] - qy;
+        dzl = (TA)x[jj * 3 + 2] - qz;
+        wl = gexp(-(((dxl * dxl + dyl * dyl) + dzl * dzl) * i2));
+      }
+    }
+    uint64_t m = __ballot(jl >= 0);
+    while (m) {
+      int src[kRows];
+      bool ok[kRows];
+      take_slots(m, src, ok);
+      int32_t jv[kRows];
+      TA a[kRows];
+#pragma unroll
+      for (int u = 0; u < kRows; ++u) {
+        jv[u] = lane_get(jl, src[u]);
+        a[u] = 0;
+      }
       for (int c0 = 0; c0 < A.C; c0 += kWave) {
         const int c = c0 + lane;
-        TA prod = 0;
-        if (c < A.C) prod = load_f<TF, TA>(g, q * A.C + c) * load_f<TF, TA>(f, j * A.C + c);
-        a += wave_sum(prod);
+        const TA gc = c0 == 0 ? g0 : (c < A.C ? load_f<TF, TA>(g, q * A.C + c) : (TA)0);
+        TA fv[kRows];
+#pragma unroll
+        for (int u = 0; u < kRows; ++u)
+          fv[u] = (ok[u] && c < A.C) ? load_f<TF, TA>(f, (int64_t)jv[u] * A.C + c) : (TA)0;
+#pragma unroll
+        for (int u = 0; u < kRows; ++u) a[u] += wave_sum(gc * fv[u]);
       }
-      s = a * w * is2;
-      cx += s * dx;
-      cy += s * dy;
-      cz += s * dz;
+#pragma unroll
+      for (int u = 0; u < kRows; ++u) {
+        if (!ok[u]) continue;
+        const TA s = a[u] * lane_get(wl, src[u]) * is2;
+        cx += s * lane_get(dxl, src[u]);
+        cy += s * lane_get(dyl, src[u]);
+        cz += s * lane_get(dzl, src[u]);
+        if (lane == src[u]) sl = s;
+      }
     }
-    if (lane == 0) {
-      pw[p] = w;
-      ps[p] = s;
-      key[p] = ok ? (uint32_t)j : (uint32_t)A.N;  // padding sorts last
+    if (t < A.K) {
+      pw[p] = wl;
+      ps[p] = sl;
+      key[p] = jl >= 0 ? (uint32_t)jl : (uint32_t)A.N;  // padding sorts last
       val[p] = (uint32_t)p;
     }
   }
@@ -168,18 +254,23 @@ __global__ __launch_bounds__(kThreads) void k_agg_bwd_pairs(AggArgs A, const TF*
   }
 }
 
-// histogram of sorted keys -> counts[key] (one thread per item)
-__global__ __launch_bounds__(kThreads) void k_key_counts(const uint32_t* __restrict__ key, int64_t n,
-                                                         int32_t* __restrict__ cnt) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n) return;
-  atomicAdd(&cnt[key[i]], 1);
-}
-
-__global__ __launch_bounds__(kThreads) void k_zero_i32(int32_t* __restrict__ a, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kThreads)
-    a[i] = 0;
+// Segment starts of ascending keys: start[b] = number of keys below b for
+// b in [0, nb], one binary search per bin (what a histogram and an exclusive
+// scan give, without atomics: padding slots share one key, and atomics on it
+// serialise).
+__global__ __launch_bounds__(kThreads) void k_bin_starts(const uint32_t* __restrict__ key, int64_t n,
+                                                         int64_t nb, int32_t* __restrict__ start) {
+  const int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (b > nb) return;
+  int64_t lo = 0, hi = n;  // first index whose key is >= b
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)key[mid] < b)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  start[b] = (int32_t)lo;
 }
 
 // pass 2, one wave per point j: neighbour-role sums over the pairs that name
@@ -192,7 +283,7 @@ __global__ __launch_bounds__(kThreads) void k_agg_bwd_points(
     const int32_t* __restrict__ pstart, const uint32_t* __restrict__ cent_sorted,
     const int32_t* __restrict__ cstart, TX* __restrict__ gx, TF* __restrict__ gf) {
   const int lane = lane_id();
-  const int64_t j = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave;
+  const int64_t j = (int64_t)blockIdx.x * kWaves + first_lane((int32_t)(threadIdx.x / kWave));
   if (j >= A.N) return;
   const TX* __restrict__ x = static_cast<const TX*>(A.x);
   const TA xj = (TA)x[j * 3], yj = (TA)x[j * 3 + 1], zj = (TA)x[j * 3 + 2];
@@ -200,21 +291,51 @@ __global__ __launch_bounds__(kThreads) void k_agg_bwd_points(
   TA ax = 0, ay = 0, az = 0;
   for (int c0 = 0; c0 < A.C; c0 += kWave) {
     const int c = c0 + lane;
+    const bool cin = c < A.C;
     TA acc = 0;
-    for (int32_t u = b; u < e; ++u) {
-      const int64_t p = pair_sorted[u];
-      const int64_t q = p / A.K;
-      if (c < A.C) acc += pw[p] * load_f<TF, TA>(g, q * A.C + c);
-      if (c0 == 0) {
-        const int64_t iq = A.qidx[q];
-        const TA s = ps[p];
-        // d/dx_j of w = -w (x_j - x_q) / sigma^2
-        ax += s * ((TA)x[iq * 3] - xj);
-        ay += s * ((TA)x[iq * 3 + 1] - yj);
-        az += s * ((TA)x[iq * 3 + 2] - zj);
+    for (int32_t u0 = b; u0 < e; u0 += kWave) {
+      // lane l: pair u0 + l, its centre, weight and (first chunk) the
+      // coordinate term s (x_q - x_j)
+      const int32_t u = u0 + lane;
+      int32_t ql = 0;
+      TA wl = 0, txl = 0, tyl = 0, tzl = 0;
+      if (u < e) {
+        const int64_t p = pair_sorted[u];
+        ql = (int32_t)(p / A.K);
+        wl = pw[p];
+        if (c0 == 0) {
+          const int64_t iq = A.qidx[ql];
+          const TA s = ps[p];
+          // d/dx_j of w = -w (x_j - x_q) / sigma^2
+          txl = s * ((TA)x[iq * 3] - xj);
+          tyl = s * ((TA)x[iq * 3 + 1] - yj);
+          tzl = s * ((TA)x[iq * 3 + 2] - zj);
+        }
+      }
+      const int n = e - u0 < kWave ? e - u0 : kWave;
+      for (int v0 = 0; v0 < n; v0 += kRows) {
+        // (broadcasts stay outside the per-lane channel test)
+        TA gv[kRows], wv[kRows];
+#pragma unroll
+        for (int u1 = 0; u1 < kRows; ++u1) {
+          const int v = v0 + u1 < n ? v0 + u1 : 0;
+          const int32_t qv = lane_get(ql, v);
+          wv[u1] = lane_get(wl, v);
+          gv[u1] = (v0 + u1 < n && cin) ? load_f<TF, TA>(g, (int64_t)qv * A.C + c) : (TA)0;
+        }
+#pragma unroll
+        for (int u1 = 0; u1 < kRows; ++u1) {
+          if (v0 + u1 >= n) continue;
+          if (cin) acc += wv[u1] * gv[u1];
+          if (c0 == 0) {
+            ax += lane_get(txl, v0 + u1);
+            ay += lane_get(tyl, v0 + u1);
+            az += lane_get(tzl, v0 + u1);
+          }
+        }
       }
     }
-    if (c < A.C) store_f<TF, TA>(gf, j * A.C + c, acc);
+    if (cin) store_f<TF, TA>(gf, j * A.C + c, acc);
   }
   const int32_t cb = cstart[j], ce = cstart[j + 1];
   for (int32_t u = cb; u < ce; ++u) {
@@ -278,7 +399,7 @@ static chs_status bwd_impl(const Alloc& al, const AggArgs& A, const TF* f, const
                            TF* gf) {
   hipStream_t st = al.stream;
   const int64_t np = A.Q * (int64_t)A.K, nk = np + A.Q;
-  Buf pw(&al), ps(&al), gq(&al), key(&al), val(&al), tk(&al), tv(&al), cnt(&al), start(&al);
+  Buf pw(&al), ps(&al), gq(&al), key(&al), val(&al), tk(&al), tv(&al), start(&al);
   CHS_TRY(pw.alloc(sizeof(TA) * (np > 0 ? np : 1)));
   CHS_TRY(ps.alloc(sizeof(TA) * (np > 0 ? np : 1)));
   CHS_TRY(gq.alloc(sizeof(TA) * 3 * (A.Q > 0 ? A.Q : 1)));
@@ -288,7 +409,6 @@ static chs_status bwd_impl(const Alloc& al, const AggArgs& A, const TF* f, const
   CHS_TRY(tv.alloc(sizeof(uint32_t) * (nk > 0 ? nk : 1)));
   // bins 0..N-1 for points, N for padding; pairs first, then centres
   const int64_t nb = A.N + 1;
-  CHS_TRY(cnt.alloc(sizeof(int32_t) * 2 * nb));
   CHS_TRY(start.alloc(sizeof(int32_t) * 2 * (nb + 1)));
   if (A.Q > 0) {
     k_agg_bwd_pairs<TX, TF, TA><<<blocks_for(A.Q), kThreads, 0, st>>>(
@@ -301,21 +421,12 @@ static chs_status bwd_impl(const Alloc& al, const AggArgs& A, const TF* f, const
   // stable regrouping: pairs by neighbour, centres by centre point
   CHS_TRY(radix_sort_u32(al, K, V, tk.as<uint32_t>(), tv.as<uint32_t>(), np, bits));
   CHS_TRY(radix_sort_u32(al, K + np, V + np, tk.as<uint32_t>(), tv.as<uint32_t>(), A.Q, bits));
-  int32_t* C0 = cnt.as<int32_t>();
   int32_t* S0 = start.as<int32_t>();
-  k_zero_i32<<<1024, kThreads, 0, st>>>(C0, 2 * nb);
+  const unsigned sb = (unsigned)((nb + 1 + kThreads - 1) / kThreads);
+  k_bin_starts<<<sb, kThreads, 0, st>>>(K, np, nb, S0);
   CHS_LAUNCH_CHECK();
-  if (np > 0) {
-    k_key_counts<<<(unsigned)((np + kThreads - 1) / kThreads), kThreads, 0, st>>>(K, np, C0);
-    CHS_LAUNCH_CHECK();
-  }
-  if (A.Q > 0) {
-    k_key_counts<<<(unsigned)((A.Q + kThreads - 1) / kThreads), kThreads, 0, st>>>(K + np, A.Q,
-                                                                                   C0 + nb);
-    CHS_LAUNCH_CHECK();
-  }
-  CHS_TRY(exclusive_scan_i32_i32(al, C0, S0, nb));
-  CHS_TRY(exclusive_scan_i32_i32(al, C0 + nb, S0 + nb + 1, nb));
+  k_bin_starts<<<sb, kThreads, 0, st>>>(K + np, A.Q, nb, S0 + nb + 1);
+  CHS_LAUNCH_CHECK();
   k_agg_bwd_points<TX, TF, TA><<<blocks_for(A.N), kThreads, 0, st>>>(
       A, g, pw.as<TA>(), ps.as<TA>(), gq.as<TA>(), V, S0, V + np, S0 + nb + 1, gx, gf);
   CHS_LAUNCH_CHECK();

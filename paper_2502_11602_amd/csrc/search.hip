@@ -648,22 +648,36 @@ struct KnnBuf {
 };
 
 // Sorted insertion of key x < best[KC-1] into best[0..KC) (ascending),
-// dropping the last entry: best'[i] = max(best[i-1], min(x, best[i])).
+// dropping the last entry.  With c[i] = x < best[i] (monotone in i, keys
+// are distinct): best'[i] = best[i-1] if c[i-1], else x if c[i], else
+// best[i]; one compare per slot.  The list passes through an empty asm so
+// that the selects are not rewritten as min/max pairs with compares of
+// their own.
 template <int KC>
 __device__ __forceinline__ void topk_insert(uint64_t (&best)[KC], uint64_t x) {
+  bool c[KC];
 #pragma unroll
-  for (int i = KC - 1; i > 0; --i) {
-    const uint64_t lo = x < best[i] ? x : best[i];
-    best[i] = best[i - 1] > lo ? best[i - 1] : lo;
+  for (int i = 0; i < KC; ++i) c[i] = x < best[i];
+  uint64_t v[KC];
+#pragma unroll
+  for (int i = 0; i < KC; ++i) {
+    v[i] = best[i];
+    asm("" : "+v"(v[i]));
   }
-  best[0] = x < best[0] ? x : best[0];
+#pragma unroll
+  for (int i = KC - 1; i > 0; --i) best[i] = c[i - 1] ? v[i - 1] : (c[i] ? x : v[i]);
+  best[0] = c[0] ? x : v[0];
 }
 
+// One compare feeds both selects.  The operands pass through an empty asm
+// first: selects over the compared values themselves would be rewritten as
+// a separate min and max, each with its own 64-bit compare.
 __device__ __forceinline__ void cmp_swap(uint64_t& a, uint64_t& b) {
   const bool s = b < a;
-  const uint64_t lo = s ? b : a, hi = s ? a : b;
-  a = lo;
-  b = hi;
+  uint64_t x = a, y = b;
+  asm("" : "+v"(x), "+v"(y));
+  a = s ? y : x;
+  b = s ? x : y;
 }
 
 template <int N>
