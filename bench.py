@@ -70,6 +70,8 @@ def counter_traffic(kernel, radius):
 # rocprofv3 runs whose summaries are committed under profiles/ (run from the
 # repository root, after `cd /tmp && export TMPDIR=/tmp`, with R the root)
 PROFILE_RUNS = {
+    "agg": "rocprofv3 --kernel-trace --stats -d $R/gpurun_out/prof_agg -o agg -- "
+           "python3 $R/bench.py --workload agg --steps 2",
     "stats": "rocprofv3 --kernel-trace --stats -d $R/gpurun_out/prof_stats -o stats -- "
              "python3 $R/bench.py --steps 5 --warmup 2 --no-cpu-baseline --no-flavor-compare "
              "--no-kernel-compare",
@@ -105,6 +107,32 @@ def _counter(con, counter):
     q = ("select dispatch_id, kernel_name, sum(value) from counters_collection "
          "where counter_name = ? group by dispatch_id")
     return {d: (n, v) for d, n, v in con.execute(q, (counter,))}
+
+
+def agg_profile_summary(stats_dir):
+    """Write the committed kernel-time summary of the aggregation workload."""
+    disp = _dispatches(_db(stats_dir))
+    agg = {}
+    for name, ms in disp:
+        a = agg.setdefault(name, [0, 0.0])
+        a[0] += 1
+        a[1] += ms
+    total = sum(v[1] for v in agg.values())
+    lines = ["# Kernel times, Gaussian aggregation workload (1 M points, 250 k centres, "
+             "64 channels)", "",
+             "Command (from the repository root R, after `cd /tmp && export TMPDIR=/tmp`):", "",
+             "    " + PROFILE_RUNS["agg"], "",
+             "Neighbour lists (k-NN, 64 nearest within 0.5 m) plus three forward and three "
+             "forward + backward passes per feature type (FP32, then BF16), the first of each a "
+             "warm-up.  Per kernel: dispatches, total and average duration.", "",
+             "| kernel | calls | total ms | avg ms | % |", "|---|---:|---:|---:|---:|"]
+    for name, (c, ms) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:20]:
+        lines.append(f"| `{name[:90]}` | {c} | {ms:.3f} | {ms / c:.4f} | {100 * ms / total:.1f} |")
+    out_dir = os.path.join(ROOT, "profiles")
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, "gauss_agg_1m.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(json.dumps({"kernels": len(agg)}))
 
 
 def profile_summary(stats_dir, fetch_dir, write_dir, radii=(0.5, 1.0, 2.0, 3.0), n=10_000_000):
@@ -539,9 +567,14 @@ def main():
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--profile-summary", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write the profiles/ summaries from rocprofv3 output directories")
+    ap.add_argument("--agg-profile-summary", metavar="STATS_DIR",
+                    help="write the aggregation workload's profiles/ summary")
     args = ap.parse_args()
     if args.profile_summary:
         profile_summary(*args.profile_summary)
+        return
+    if args.agg_profile_summary:
+        agg_profile_summary(args.agg_profile_summary)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
