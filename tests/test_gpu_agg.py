@@ -83,6 +83,34 @@ def test_agg_fp64_exact_and_gradcheck():
                                     eps=1e-6, atol=1e-7, rtol=1e-5, fast_mode=True)
 
 
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-4), (torch.float64, 1e-10)])
+def test_agg_long_lists_and_ragged_channels(dtype, tol):
+    """More than 64 slots per list and channel counts that are not a
+    multiple of 64 (several slot and channel chunks per wave), with padding
+    in the middle of lists and out-of-range entries, which are skipped."""
+    from paper_2502_11602_amd import GaussAgg
+    c, x32, q, nbr = _case(6_000, 1_500, 70, seed=45, k=64, r_max=1.0)
+    dev = x32.device
+    # 100 slots: the 64 nearest, then 36 neighbours of the previous centre
+    nbr = torch.cat([nbr, nbr[:, :36].roll(1, 0)], 1).contiguous()
+    nbr[::7, 3] = -1
+    nbr[::11, 70] = -5
+    nbr[::13, 80] = x32.shape[0] + 2
+    assert (nbr >= 0).sum(1).float().mean() > 64  # second slot chunk in use
+    x = x32.to(dtype).clone().requires_grad_(True)
+    f = torch.from_numpy(c["f"]).to(dev).to(dtype).requires_grad_(True)
+    out = GaussAgg.apply(x, f, q, nbr, c["sigma"])
+    g = torch.randn(out.shape, dtype=torch.float64,
+                    generator=torch.Generator().manual_seed(5)).to(dev).to(dtype)
+    out.backward(g)
+    ok = (nbr >= 0) & (nbr < x32.shape[0])
+    nclean = torch.where(ok, nbr, torch.full_like(nbr, -1))
+    ro, rgx, rgf = _reference(x, q, nclean, f, g, c["sigma"])
+    assert _rel(out.detach().double().cpu().numpy(), ro) <= tol
+    assert _rel(x.grad.double().cpu().numpy(), rgx) <= tol
+    assert _rel(f.grad.double().cpu().numpy(), rgf) <= tol
+
+
 def test_agg_deterministic_and_special_cases():
     from paper_2502_11602_amd import gauss_aggregate
     c, x32, q, nbr = _case(20_000, 4_000, 64, seed=7)
