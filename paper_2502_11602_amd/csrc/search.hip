@@ -433,14 +433,24 @@ struct RadiusArgs {
 // instruction, one per half-wave) instead of 64 scattered 4-byte stores per
 // candidate, which the memory system would write back as 64 partial lines.
 // Every store is also checked against its row's end.
-constexpr int kStage = 32;                 // entries per lane
-constexpr int kStageStride = kStage + 1;   // padded against LDS bank conflicts
 constexpr int kGroup = 8;                   // candidates loaded together in the fill
 constexpr int kFlushUnroll = 4;             // lane pairs written per flush step
-// A flush writes only the lanes holding at least kMinFlush entries (the
-// others keep theirs for the next flush), so that stores carry more entries.
-constexpr int kMinFlush = 12;
-static_assert(kMinFlush <= kStage - kGroup, "a kept run must leave room for a group");
+// Stage of ST entries per lane.  A flush writes only the lanes holding at
+// least min_flush entries (the others keep theirs for the next flush), so
+// that stores carry more entries.  The stage's LDS bounds the waves per
+// CU: short rows take the small stage (more waves in flight), long rows
+// the larger one (fewer flushes).
+template <int ST>
+struct Stage {
+  static constexpr int size = ST;
+  static constexpr int stride = ST + 1;  // odd, against LDS bank conflicts
+  static constexpr int min_flush = ST <= 16 ? 6 : (ST <= 24 ? 10 : 12);
+  static_assert(min_flush <= ST - kGroup, "a kept run must leave room for a group");
+};
+constexpr int kStageShort = 16, kStageMid = 24, kStageLong = 32;
+// mean row lengths (neighbours per query) from which the fill takes the
+// middle and the long stage
+constexpr int64_t kMidRows = 64, kLongRows = 256;
 
 // Where a lane's staged entries go: the row position and how many of them
 // are written (published once per flush, read by the half-waves).
@@ -450,11 +460,11 @@ struct alignas(16) RowSlot {
 };
 
 // FINAL: the lane's last flush, everything staged is written.
-template <bool FINAL>
+template <bool FINAL, int ST>
 __device__ __forceinline__ void flush_stage(const int32_t* seg_base, RowSlot* rows, int lane,
                                             int& nb, int64_t& wpos, int64_t wend,
                                             int32_t* __restrict__ nbr) {
-  const int32_t used = (FINAL || nb >= kMinFlush) ? nb : 0;
+  const int32_t used = (FINAL || nb >= Stage<ST>::min_flush) ? nb : 0;
   const int64_t room = wend - wpos;
   RowSlot slot;
   slot.pos = wpos;
@@ -484,7 +494,7 @@ __device__ __forceinline__ void flush_stage(const int32_t* seg_base, RowSlot* ro
 #pragma unroll
     for (int u = 0; u < kFlushUnroll; ++u) {
       r[u] = rows[src[u]];
-      v[u] = seg_base[src[u] * kStageStride + i];
+      v[u] = seg_base[src[u] * Stage<ST>::stride + i];
     }
     // keep the reads ahead of every store (the compiler would otherwise sink
     // some of them into the stores' branches, one LDS round trip each)
@@ -500,7 +510,7 @@ __device__ __forceinline__ void flush_stage(const int32_t* seg_base, RowSlot* ro
   nb -= used;
 }
 
-template <bool FILL, bool MULTI, int FL, int KS>
+template <bool FILL, bool MULTI, int FL, int KS, int ST>
 __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it, int lane,
                                             int32_t* seg_base, RowSlot* rows) {
   const Grid g = MULTI ? A.W.tiles[it.tile] : A.g0;
@@ -521,7 +531,7 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
   int32_t cnt = 0;
   int64_t wpos = 0, wend = 0;
   int nb = 0;
-  int32_t* my_seg = seg_base + (FILL ? lane * kStageStride : 0);
+  int32_t* my_seg = seg_base + (FILL ? lane * Stage<ST>::stride : 0);
   if (FILL && active) {
     wpos = A.offsets[qid];
     wend = A.offsets[qid + 1];
@@ -561,7 +571,7 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
             // and the stage is flushed whenever a lane could overflow it in
             // the next group.  Every candidate is written to the next free
             // slot and kept only if it matches (no divergent branch per
-            // candidate); a stage never holds more than kStage - kGroup
+            // candidate); a stage never holds more than ST - kGroup
             // entries before a group, so the slot is always in range.
             const_pts cp = as_const(A.pts);
             int32_t p = rb;
@@ -574,41 +584,43 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
                 my_seg[nb] = __float_as_int(P[u].w) - poff;
                 nb += inside<KS>(q, P[u], rr, R) ? 1 : 0;
               }
-              if (__ballot(nb > kStage - kGroup)) flush_stage<false>(seg_base, rows, lane, nb, wpos, wend, A.nbr);
+              if (__ballot(nb > ST - kGroup)) flush_stage<false, ST>(seg_base, rows, lane, nb, wpos, wend, A.nbr);
             }
             for (; p < re; ++p) {
               const float4 P = load_const(cp, p);
               my_seg[nb] = __float_as_int(P.w) - poff;
               nb += inside<KS>(q, P, rr, R) ? 1 : 0;
-              if (__ballot(nb > kStage - kGroup)) flush_stage<false>(seg_base, rows, lane, nb, wpos, wend, A.nbr);
+              if (__ballot(nb > ST - kGroup)) flush_stage<false, ST>(seg_base, rows, lane, nb, wpos, wend, A.nbr);
             }
           }
         }
       }
     }
   }
-  if (FILL) flush_stage<true>(seg_base, rows, lane, nb, wpos, wend, A.nbr);
+  if (FILL) flush_stage<true, ST>(seg_base, rows, lane, nb, wpos, wend, A.nbr);
   if (!FILL && in && (int64_t)qid < A.W.nq) A.counts[qid] = active ? cnt : 0;
 }
 
 // MULTI: per-item tile lookups and, if a counter is given, a persistent
 // loop over work items; otherwise one wave per item with tile 0's grid.
-template <bool FILL, bool MULTI, int FL, int KS>
+// ST: entries per lane of the fill's stage (unused by the count pass)
+template <bool FILL, bool MULTI, int FL, int KS, int ST>
 __global__ __launch_bounds__(kThreads) void k_radius(RadiusArgs A) {
-  __shared__ int32_t s_stage[FILL ? kWavesPerBlock * kWave * kStageStride : 1];
+  __shared__ int32_t s_stage[FILL ? kWavesPerBlock * kWave * Stage<ST>::stride : 1];
   __shared__ RowSlot s_rows[FILL ? kWavesPerBlock * kWave : 1];
   const int w = threadIdx.x / kWave, lane = lane_id();
-  int32_t* seg_base = s_stage + (FILL ? w * kWave * kStageStride : 0);
+  int32_t* seg_base = s_stage + (FILL ? w * kWave * Stage<ST>::stride : 0);
   RowSlot* rows = s_rows + (FILL ? w * kWave : 0);
   int64_t own = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
   if (!MULTI) {
-    if (own < A.W.nwaves) radius_item<FILL, false, FL, KS>(A, item_of(A.W, own), lane, seg_base, rows);
+    if (own < A.W.nwaves)
+      radius_item<FILL, false, FL, KS, ST>(A, item_of(A.W, own), lane, seg_base, rows);
     return;
   }
   while (true) {
     const int64_t item = next_item(A.W, &own, lane);
     if (item >= A.W.nwaves) break;
-    radius_item<FILL, true, FL, KS>(A, item_of(A.W, item), lane, seg_base, rows);
+    radius_item<FILL, true, FL, KS, ST>(A, item_of(A.W, item), lane, seg_base, rows);
   }
 }
 
@@ -1094,31 +1106,49 @@ static chs_status launch_dims(chs_index ix, const QueryPlan& plan, hipStream_t s
   return CHS_OK;
 }
 
-// kernel instance for the index's flavor, launch mode and search kernel
-template <bool FILL, int KS>
+// kernel instance for the index's flavor, launch mode, search kernel and
+// (fill) stage size
+template <bool FILL, int KS, int ST>
 static void launch_radius_ks(chs_index ix, unsigned nb, hipStream_t st, const RadiusArgs& A) {
   const bool mt = multi(ix);
   switch (ix->flavor) {
     case CHS_DENSE:
-      mt ? k_radius<FILL, true, CHS_DENSE, KS><<<nb, kThreads, 0, st>>>(A)
-         : k_radius<FILL, false, CHS_DENSE, KS><<<nb, kThreads, 0, st>>>(A);
+      mt ? k_radius<FILL, true, CHS_DENSE, KS, ST><<<nb, kThreads, 0, st>>>(A)
+         : k_radius<FILL, false, CHS_DENSE, KS, ST><<<nb, kThreads, 0, st>>>(A);
       break;
     case CHS_SPARSE:
-      mt ? k_radius<FILL, true, CHS_SPARSE, KS><<<nb, kThreads, 0, st>>>(A)
-         : k_radius<FILL, false, CHS_SPARSE, KS><<<nb, kThreads, 0, st>>>(A);
+      mt ? k_radius<FILL, true, CHS_SPARSE, KS, ST><<<nb, kThreads, 0, st>>>(A)
+         : k_radius<FILL, false, CHS_SPARSE, KS, ST><<<nb, kThreads, 0, st>>>(A);
       break;
     default:
-      mt ? k_radius<FILL, true, CHS_MIXED, KS><<<nb, kThreads, 0, st>>>(A)
-         : k_radius<FILL, false, CHS_MIXED, KS><<<nb, kThreads, 0, st>>>(A);
+      mt ? k_radius<FILL, true, CHS_MIXED, KS, ST><<<nb, kThreads, 0, st>>>(A)
+         : k_radius<FILL, false, CHS_MIXED, KS, ST><<<nb, kThreads, 0, st>>>(A);
   }
 }
 
+template <bool FILL, int ST>
+static void launch_radius_st(chs_index ix, unsigned nb, hipStream_t st, const RadiusArgs& A,
+                             int32_t kernel) {
+  if (kernel == CHS_KERNEL_CUBE) launch_radius_ks<FILL, kCube, ST>(ix, nb, st, A);
+  else if (kernel == CHS_KERNEL_CYLINDER) launch_radius_ks<FILL, kCylinder, ST>(ix, nb, st, A);
+  else launch_radius_ks<FILL, kSphere, ST>(ix, nb, st, A);
+}
+
+// mean_rows: the fill's mean row length (neighbours per query)
 template <bool FILL>
 static void launch_radius(chs_index ix, unsigned nb, hipStream_t st, const RadiusArgs& A,
-                          int32_t kernel) {
-  if (kernel == CHS_KERNEL_CUBE) launch_radius_ks<FILL, kCube>(ix, nb, st, A);
-  else if (kernel == CHS_KERNEL_CYLINDER) launch_radius_ks<FILL, kCylinder>(ix, nb, st, A);
-  else launch_radius_ks<FILL, kSphere>(ix, nb, st, A);
+                          int32_t kernel, int64_t mean_rows = 0) {
+  if constexpr (FILL) {
+    if (mean_rows >= kLongRows) {
+      launch_radius_st<FILL, kStageLong>(ix, nb, st, A, kernel);
+      return;
+    }
+    if (mean_rows >= kMidRows) {
+      launch_radius_st<FILL, kStageMid>(ix, nb, st, A, kernel);
+      return;
+    }
+  }
+  launch_radius_st<FILL, kStageShort>(ix, nb, st, A, kernel);
 }
 
 template <int KC, int SCHED>
@@ -1166,14 +1196,15 @@ static chs_status radius_count_impl(chs_index ix, const QueryPlan& plan, int32_t
 }
 
 static chs_status radius_fill_impl(chs_index ix, const QueryPlan& plan, int32_t kernel, float r,
-                                   const int64_t* offsets, int32_t* nbr, hipStream_t st) {
+                                   const int64_t* offsets, int32_t* nbr, int64_t total,
+                                   hipStream_t st) {
   if (plan.nq == 0) return CHS_OK;
   int32_t* ctr;
   unsigned nb;
   CHS_TRY(launch_dims(ix, plan, st, &ctr, &nb));
   RadiusArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), r, nullptr,
                offsets, nbr};
-  launch_radius<true>(ix, nb, st, A, kernel);
+  launch_radius<true>(ix, nb, st, A, kernel, total / plan.nq);
   CHS_LAUNCH_CHECK();
   return CHS_OK;
 }
@@ -1235,7 +1266,7 @@ extern "C" chs_status chs_kernel_fill(chs_index ix, const chs_queries* qs, int32
   al.stream = st;
   QueryPlan plan(&al);
   CHS_TRY(plan_queries(ix, qs, &plan, st));
-  CHS_TRY(radius_fill_impl(ix, plan, kernel, r, offsets, nbr, st));
+  CHS_TRY(radius_fill_impl(ix, plan, kernel, r, offsets, nbr, total, st));
   return CHS_OK;
 }
 
@@ -1274,7 +1305,7 @@ extern "C" chs_status chs_kernel_search(chs_index ix, const chs_queries* qs, int
       set_error("allocator returned NULL for %lld neighbour indices", (long long)tot);
       return CHS_E_NOMEM;
     }
-    chs_status s = radius_fill_impl(ix, plan, kernel, r, offsets, out, st);
+    chs_status s = radius_fill_impl(ix, plan, kernel, r, offsets, out, tot, st);
     if (s != CHS_OK) {
       out_al.put(out);
       return s;
