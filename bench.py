@@ -306,7 +306,7 @@ def run_agg(args):
     ix = GridIndex(x64, cell=args.agg_cell, flavor="dense")
     nbr = neighbour_lists(ix, q, k=K, r_max=c["r"])
     t_nbr = timed(lambda: neighbour_lists(ix, q, k=K, r_max=c["r"]), reps)
-    x32 = recentred(x64, ix)
+    x32 = recentred(ix)
     P = int((nbr >= 0).sum())
     res = {}
     for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
@@ -627,8 +627,7 @@ def main():
         ev["start"].record()
         ix = GridIndex(x, cell=args.cell, flavor=flavor)
         ev["build"] = E(); ev["build"].record()
-        # the "every point" query order is planned by the first search on the
-        # index and cached on it, so the first count below includes it
+        # (the build also plans the processing order of "every point" queries)
         totals = {}
         for r in radii:
             off, tot = ix.radius_count(r)

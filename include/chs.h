@@ -17,6 +17,9 @@
  *    are allocated by the caller.  Memory the library keeps (the index) or
  *    needs temporarily comes from the `chs_allocator` given to chs_build; a
  *    NULL allocator means stream-ordered hipMallocAsync / hipFreeAsync.
+ *  - Temporaries of a call are allocated for, and freed on, the call's
+ *    stream.  Searches on one index may run concurrently on different
+ *    streams: each call has its own work counter and query plan.
  *  - Calls never abort.  They return a chs_status; on failure the message of
  *    chs_last_error() says why, the caller's outputs are left untouched
  *    unless stated otherwise, and nothing leaks.  Arguments are validated on
@@ -97,11 +100,15 @@ typedef struct chs_queries {
  * + 1 (Eq. 3), each point's voxel (Eq. 5, 0-based, clamped to n_a - 1) and
  * global index g = (i*n_y + j)*n_z + k (Eq. 6-7), the per-voxel counts, their
  * exclusive prefix sum and the stable scatter of the points into voxel order
- * (ascending g, then ascending original index), and the flavor's voxel map.
- * Synchronises `stream` to size the grid from the bounding box and the
- * voxel tables from the number of non-empty voxels (and, for MIXED, the
- * per-slice counts).  n in [1, 2^31 - 1].  Non-finite coordinates give CHS_E_INVALID; a dense
- * grid above max_dense_cells gives CHS_E_CAPACITY.  On success *out (host)
+ * (ascending g, then ascending original index), and the flavor's voxel map;
+ * then the processing order of "every point" queries (a Hilbert order over
+ * the voxel columns), so that such searches plan nothing.  Synchronises
+ * `stream` to size the grid from the bounding box and the voxel tables from
+ * the number of non-empty voxels (and, for MIXED, the per-slice counts).
+ * n in [1, 2^31 - 1].  Non-finite coordinates give CHS_E_INVALID; a dense
+ * grid above max_dense_cells gives CHS_E_CAPACITY; an allocator returning
+ * NULL gives CHS_E_NOMEM (everything allocated so far is released and *out
+ * is untouched).  On success *out (host)
  * owns its device memory until chs_free. */
 chs_status chs_build(const double* xyz, int64_t n, const chs_build_params* params,
                      const chs_allocator* alloc, hipStream_t stream, chs_index* out);
@@ -120,8 +127,11 @@ typedef struct chs_index_info_t {
   int32_t reserved;
 } chs_index_info_t;
 
-/* Host-side description of a built index (for a batched index: tile 0's
- * geometry and the totals).  No device work. */
+/* Host-side description of a built index: the bounding-box corner p- and
+ * the recentred extent (Section 3.1, Eq. 1-2), the voxel edges and the grid
+ * size n_x, n_y, n_z (Section 3.2, Eq. 3), the number of non-empty voxels
+ * and, for MIXED, of slices stored densely (Section 3.3.3).  For a batched
+ * index: tile 0's geometry and the totals.  No device work. */
 chs_status chs_index_info(chs_index index, chs_index_info_t* out /* host */);
 
 /* Batched build: ntiles independent clouds stored back to back in xyz
@@ -141,7 +151,9 @@ chs_status chs_build_batch(const double* xyz, int64_t n, const int64_t* tile_off
 /* Geometry of one tile of a batched index (n_nonempty is -1). */
 chs_status chs_tile_info(chs_index index, int32_t tile, chs_index_info_t* out /* host */);
 
-/* CHS_OPT_PERSISTENT (default: on for batched indexes, off otherwise):
+/* Options of a built index (the searches' launch and schedule; results never
+ * depend on them).
+ * CHS_OPT_PERSISTENT (default: on for batched indexes, off otherwise):
  * searches launch one wave per hardware slot and the waves pull 64-query
  * work items (largest tiles first) from a device counter until none is left,
  * instead of one wave per work item.  Results are identical either way.
@@ -152,11 +164,20 @@ chs_status chs_tile_info(chs_index index, int32_t tile, chs_index_info_t* out /*
  * the nearest wall of the query's voxel (Eq. 11) and grows from the density
  * of the candidates within it (Eq. 12), a query being done once k of them
  * lie within the radius.  Results are identical; only the cost differs. */
-typedef enum chs_option { CHS_OPT_PERSISTENT = 1, CHS_OPT_KNN_SCHEDULE = 4 } chs_option;
+/* CHS_OPT_FILL_STAGE (default 0): the radius fill stages each query's
+ * matches in on-chip memory (LDS) before writing them out, 16, 24 or 32
+ * entries per query; 0 picks the size from the mean row length total / nq.
+ * Results are identical. */
+typedef enum chs_option {
+  CHS_OPT_PERSISTENT = 1,
+  CHS_OPT_KNN_SCHEDULE = 4,
+  CHS_OPT_FILL_STAGE = 5
+} chs_option;
 chs_status chs_index_set_option(chs_index index, int32_t option, int64_t value);
 
 /* Device arrays of a built index, borrowed (valid until chs_free, never to
- * be written).  perm[pos] = original index of the pos-th stored point;
+ * be written): the reordered cloud of Section 3.5 ("Reordering", points
+ * stored voxel by voxel) and the voxel maps of Section 3.3.  perm[pos] = original index of the pos-th stored point;
  * inv_perm = its inverse; sorted_xyz = SoA [3][n] FP32 recentred coordinates
  * in stored order; points = [n] x,y,z,FP32 + original index (int32 bits) in
  * stored order; cell_keys [M] = ascending non-empty global voxel indices
@@ -177,6 +198,12 @@ typedef struct chs_index_arrays_t {
 
 chs_status chs_index_arrays(chs_index index, chs_index_arrays_t* out /* host */);
 
+/* The index's FP32 coordinates in input order: out [n,3] (FP32, device,
+ * caller-allocated) receives fl32(p - p-) for every point p, the recentring
+ * of Section 3.1 (Eq. 1) that every distance of the searches uses; each tile
+ * of a batched index in its own frame.  Enqueued on `stream`. */
+chs_status chs_index_coords(chs_index index, float* out, hipStream_t stream);
+
 /* Fixed-radius search, count pass (Alg. 1 with a spherical kernel B(c, r),
  * Section 3.4.1): offsets [nq+1] (int64, device) receives the exclusive
  * prefix sum of the per-query neighbour counts |{p : D(c, p) <= fl32(r*r)}|,
@@ -185,18 +212,26 @@ chs_status chs_index_arrays(chs_index index, chs_index_arrays_t* out /* host */)
 chs_status chs_radius_count(chs_index index, const chs_queries* queries, float r,
                             int64_t* offsets, int64_t* total, hipStream_t stream);
 
-/* Fill pass: writes the original indices of each query's neighbours into
- * nbr[offsets[q] .. offsets[q+1]) (int32, device, `total` entries, as given
- * by chs_radius_count for the same queries and r).  The order inside a row
- * is deterministic but unspecified (the neighbour relation is a set). */
+/* Fill pass of Alg. 1 (Section 3.4.1; the points inside the kernel are
+ * appended to the query's list): writes the original indices of each
+ * query's neighbours into nbr[offsets[q] .. offsets[q+1]) (int32, device,
+ * `total` entries, as given by chs_radius_count for the same queries and r).
+ * The order inside a row is deterministic but unspecified (the neighbour
+ * relation is a set).  Every write stays inside nbr[0, total): a row is
+ * clipped at total, and a row with offsets[q] < 0 or offsets[q] >
+ * offsets[q+1] is not written, so offsets that belong to other queries or
+ * another r give wrong rows but never write outside nbr. */
 chs_status chs_radius_fill(chs_index index, const chs_queries* queries, float r,
                            const int64_t* offsets, int32_t* nbr, int64_t total,
                            hipStream_t stream);
 
-/* count + allocation of the neighbour array through `alloc` (NULL = the
- * index's allocator) + fill.  *nbr (host) receives the device pointer, which
- * the caller releases with the same allocator (or hipFree for NULL); it is
- * NULL when total is 0.  Synchronises `stream` once. */
+/* The whole fixed-radius search of Alg. 1 (Section 3.4.1): count +
+ * allocation of the neighbour array through `alloc` (NULL = the index's
+ * allocator) + fill.  *nbr (host) receives the device pointer, which the
+ * caller releases with the same allocator (or hipFree for NULL); it is NULL
+ * when total is 0.  Synchronises `stream` once.  If the allocation fails
+ * (CHS_E_NOMEM) offsets already hold the count pass's result and *nbr,
+ * *total are untouched. */
 chs_status chs_radius_search(chs_index index, const chs_queries* queries, float r,
                              const chs_allocator* alloc, int64_t* offsets, int32_t** nbr,
                              int64_t* total, hipStream_t stream);
@@ -242,6 +277,8 @@ chs_status chs_knn(chs_index index, const chs_queries* queries, int32_t k, float
  *   x     [N,3]  coordinates (recentred), x_dtype
  *   f     [N,C]  features, f_dtype;   out, grad_out, grad_f [Q,C] f_dtype
  *   qidx  [Q]    centre point of each query; nbr [Q,K] int32
+ * Sizes: 1 <= N < 2^31 - 1, C >= 1 and Q * (K + 1) <= 2^31 - 1 (the backward
+ * regroups the pair slots with 32-bit positions), else CHS_E_INVALID.
  * dtype pairs: (CHS_F32, CHS_F32), (CHS_F32, CHS_BF16) computing in FP32, and
  * (CHS_F64, CHS_F64) computing in FP64; others give CHS_E_UNSUPPORTED.  Sums
  * run in a fixed order, so results are bitwise reproducible. */

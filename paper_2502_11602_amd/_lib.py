@@ -53,6 +53,7 @@ SIGNATURES = {
     "chs_tile_info": (c_int32, [c_void_p, c_int32, ctypes.POINTER(IndexInfo)]),
     "chs_index_set_option": (c_int32, [c_void_p, c_int32, c_int64]),
     "chs_index_arrays": (c_int32, [c_void_p, ctypes.POINTER(IndexArrays)]),
+    "chs_index_coords": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "chs_radius_count": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_float, c_void_p,
                                    ctypes.POINTER(c_int64), c_void_p]),
     "chs_radius_fill": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_float, c_void_p, c_void_p,

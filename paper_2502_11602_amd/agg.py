@@ -68,7 +68,7 @@ def neighbour_lists(index, qidx, k=64, r_max=0.5):
     return idx
 
 
-def recentred(xyz64, index):
-    """FP32 coordinates in the index's frame (x - p-, rounded once)."""
-    o = torch.tensor(index.info()["origin"], dtype=torch.float64, device=xyz64.device)
-    return (xyz64 - o).to(torch.float32)
+def recentred(index):
+    """FP32 coordinates in the index's frame, in input order: the library's
+    own recentring (Section 3.1, Eq. 1), the same values its searches use."""
+    return index.coords()

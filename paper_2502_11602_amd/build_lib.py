@@ -37,12 +37,26 @@ def sources():
 
 
 def build(verbose=False, extra=()):
-    """Always recompiles; writes libchs.so next to this file."""
+    """Always recompiles (one hipcc process per source, in parallel, then one
+    link); writes libchs.so next to this file."""
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *extra, "-o", tmp, *sources()]
+    objs, procs = [], []
+    for src in sources():
+        obj = os.path.join(CSRC, os.path.basename(src) + ".o")
+        objs.append(obj)
+        cmd = [HIPCC, *[f for f in FLAGS if f != "-shared"], *extra, "-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
+    failed = [cmd for cmd, pr in procs if pr.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
+    link = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+        print(" ".join(link), flush=True)
+    subprocess.check_call(link)
+    for obj in objs:
+        os.remove(obj)
     os.replace(tmp, LIB)
     return LIB
 

@@ -360,8 +360,10 @@ static chs_status check_agg(const void* x, const int32_t* qidx, const int32_t* n
     set_error("x, f, qidx or nbr is NULL");
     return CHS_E_INVALID;
   }
-  if (N < 1 || N > (int64_t)INT32_MAX - 1 || Q < 0 || K < 0 || C < 1 ||
-      Q * (int64_t)K + Q > (int64_t)UINT32_MAX) {
+  // the backward regroups the Q*K pair slots (plus Q centre slots) with
+  // int32 positions
+  if (N < 1 || N > (int64_t)INT32_MAX - 1 || Q < 0 || K < 0 || C < 1 || K > (int64_t)INT32_MAX ||
+      Q > (int64_t)INT32_MAX || Q * (int64_t)K + Q > (int64_t)INT32_MAX) {
     set_error("sizes out of range (N=%lld Q=%lld K=%d C=%d)", (long long)N, (long long)Q, K, C);
     return CHS_E_INVALID;
   }

@@ -143,6 +143,18 @@ __global__ __launch_bounds__(kThreads) void k_gather_points(
   inv_perm[p] = (int32_t)pos;
 }
 
+// FP32 coordinates in input order (each tile in its own recentred frame).
+__global__ __launch_bounds__(kThreads) void k_coords(const float4* __restrict__ pts,
+                                                     const int32_t* __restrict__ inv_perm,
+                                                     int64_t n, float* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (p >= n) return;
+  const float4 c = pts[inv_perm[p]];
+  out[3 * p] = c.x;
+  out[3 * p + 1] = c.y;
+  out[3 * p + 2] = c.z;
+}
+
 // ---------------------------------------------------------------- non-empty voxels
 template <class K>
 __global__ __launch_bounds__(kThreads) void k_run_heads(const K* __restrict__ skeys, int64_t n,
@@ -537,6 +549,9 @@ static chs_status build_impl(chs_index ix, const double* xyz, int64_t n, const i
   if (ix->flavor == CHS_DENSE) CHS_TRY(build_dense(ix));
   if (ix->flavor == CHS_SPARSE) CHS_TRY(build_sparse(ix));
   if (ix->flavor == CHS_MIXED) CHS_TRY(build_mixed(ix));
+  // the processing order of "every point" queries (searches then plan
+  // nothing for them)
+  CHS_TRY(plan_every_point(ix, st));
   // ukeys, ustart, the tile table and the host vectors above are in use
   // by queued work; wait before they go out of scope
   CHS_HIP(hipStreamSynchronize(st));
@@ -640,6 +655,14 @@ extern "C" chs_status chs_index_set_option(chs_index ix, int32_t option, int64_t
     ix->persistent = value != 0;
     return CHS_OK;
   }
+  if (option == CHS_OPT_FILL_STAGE) {
+    if (value != 0 && value != 16 && value != 24 && value != 32) {
+      set_error("fill stage must be 0 (by mean row length), 16, 24 or 32");
+      return CHS_E_INVALID;
+    }
+    ix->fill_stage = (int32_t)value;
+    return CHS_OK;
+  }
   if (option == CHS_OPT_KNN_SCHEDULE) {
     if (value != 0 && value != 1) {
       set_error("k-NN schedule must be 0 (rings) or 1 (density growth)");
@@ -708,5 +731,16 @@ extern "C" chs_status chs_index_arrays(chs_index ix, chs_index_arrays_t* out) {
   out->cell_start = ix->ustart;
   out->dense_start = ix->flavor == CHS_DENSE ? ix->dstart : nullptr;
   out->slice_dense = ix->flavor == CHS_MIXED ? ix->slice_dense : nullptr;
+  return CHS_OK;
+}
+
+extern "C" chs_status chs_index_coords(chs_index ix, float* out, hipStream_t st) {
+  clear_error();
+  if (!ix || !out) {
+    set_error("index or out is NULL");
+    return CHS_E_INVALID;
+  }
+  k_coords<<<grid_for(ix->n), kThreads, 0, st>>>(ix->pts, ix->inv_perm, ix->n, out);
+  CHS_LAUNCH_CHECK();
   return CHS_OK;
 }

@@ -114,6 +114,7 @@ struct chs_index_s {
   int64_t max_dense = (int64_t)INT32_MAX - 1;
   bool persistent = false;  // searches pull waves from a work counter
   bool knn_density = false;  // k-NN with the density-growth schedule of Alg. 2
+  int32_t fill_stage = 0;    // radius fill: LDS entries per lane (0: by mean row length)
   // per tile, host copies (tile 0 is the whole cloud of a plain index)
   std::vector<chs::Grid> tiles;
   std::vector<double> origin;   // [3 * ntiles]
@@ -143,7 +144,6 @@ struct chs_index_s {
   int32_t* wave_start = nullptr;  //   first query of each wave
   int32_t* tile_qend = nullptr;   //   end of each tile's queries
   int64_t allq_waves = 0;
-  int32_t* work_counter = nullptr;  // persistent launches
   std::vector<void*> owned;
 
   int64_t ncells_limit() const { return max_dense; }
@@ -407,6 +407,14 @@ struct QueryPlan {
   explicit QueryPlan(const Alloc* al) : q4(al) {}
 };
 chs_status plan_queries(chs_index ix, const chs_queries* qs, QueryPlan* plan, hipStream_t stream);
+chs_status plan_every_point(chs_index ix, hipStream_t stream);
+
+// Host validation of a query batch against the index.
+chs_status check_queries(chs_index ix, const chs_queries* qs);
+
+// chs_knn with the temporaries taken from `al` (validates its arguments).
+chs_status knn_impl(chs_index ix, const chs_queries* qs, int32_t k, float r_max, int32_t* idx,
+                    float* d2, const Alloc& al, hipStream_t stream);
 
 int ceil_log2(uint64_t v);
 

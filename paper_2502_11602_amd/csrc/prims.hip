@@ -132,10 +132,17 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const Tin* __restri
   }
 }
 
+template <class T>
+__global__ void k_store_zero(T* out) {
+  if (threadIdx.x == 0) *out = (T)0;
+}
+
 template <class Tin, class Tout>
 static chs_status scan_impl(const Alloc& al, const Tin* in, Tout* out, int64_t n) {
   if (n <= 0) {
-    CHS_HIP(hipMemsetAsync(out, 0, sizeof(Tout), al.stream));
+    // a kernel rather than a memset, so that captured graphs replay it
+    k_store_zero<Tout><<<1, kWave, 0, al.stream>>>(out);
+    CHS_LAUNCH_CHECK();
     return CHS_OK;
   }
   const int64_t nb = (n + kScanTile - 1) / kScanTile;

@@ -61,8 +61,8 @@ __global__ __launch_bounds__(kThreads) void k_plan_keys(
     int mode, const double* __restrict__ xyz, const int32_t* __restrict__ pidx, int64_t nq,
     const float4* __restrict__ pts, const int32_t* __restrict__ inv_perm,
     const int32_t* __restrict__ perm, int64_t npts, const Grid* __restrict__ tiles,
-    const TilePlan* __restrict__ tplan, const int64_t* __restrict__ toff, int ntiles,
-    double ox, double oy, double oz, int lshift, int total_bits, K* __restrict__ keys,
+    TilePlan tp0, const TilePlan* __restrict__ tplan, const int64_t* __restrict__ toff,
+    int ntiles, double ox, double oy, double oz, int lshift, int total_bits, K* __restrict__ keys,
     uint32_t* __restrict__ vals, float4* __restrict__ tmp) {
   const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (q >= nq) return;
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kThreads) void k_plan_keys(
     c = make_float4(v[0], v[1], v[2], 0.f);
   }
   const Grid g = tiles[t];
-  const TilePlan tp = tplan[t];
+  const TilePlan tp = ntiles > 1 ? tplan[t] : tp0;
   int64_t cell[3] = {0, 0, 0};
   const float cc[3] = {c.x, c.y, c.z};
 #pragma unroll
@@ -148,15 +148,19 @@ static chs_status plan_impl(chs_index ix, int mode, const double* xyz, const int
   CHS_TRY(vals.alloc(4 * nq));
   CHS_TRY(tv.alloc(4 * nq));
   CHS_TRY(tmp.alloc(sizeof(float4) * nq));
-  CHS_TRY(tp_d.alloc(sizeof(TilePlan) * T));
-  CHS_TRY(toff_d.alloc(sizeof(int64_t) * (T + 1)));
-  CHS_HIP(hipMemcpyAsync(tp_d.p, tp.data(), sizeof(TilePlan) * T, hipMemcpyHostToDevice, st));
-  CHS_HIP(hipMemcpyAsync(toff_d.p, ix->tile_off.data(), sizeof(int64_t) * (T + 1),
-                         hipMemcpyHostToDevice, st));
+  if (T > 1) {
+    // (only the build plans several tiles; it waits for the stream before
+    // these host vectors go out of scope)
+    CHS_TRY(tp_d.alloc(sizeof(TilePlan) * T));
+    CHS_TRY(toff_d.alloc(sizeof(int64_t) * (T + 1)));
+    CHS_HIP(hipMemcpyAsync(tp_d.p, tp.data(), sizeof(TilePlan) * T, hipMemcpyHostToDevice, st));
+    CHS_HIP(hipMemcpyAsync(toff_d.p, ix->tile_off.data(), sizeof(int64_t) * (T + 1),
+                           hipMemcpyHostToDevice, st));
+  }
   const double* o = ix->origin.data();
   if (wide) {
     k_plan_keys<uint64_t><<<grid_for(nq), kThreads, 0, st>>>(
-        mode, xyz, pidx, nq, ix->pts, ix->inv_perm, ix->perm, ix->n, ix->tiles_d,
+        mode, xyz, pidx, nq, ix->pts, ix->inv_perm, ix->perm, ix->n, ix->tiles_d, tp[0],
         tp_d.as<TilePlan>(), toff_d.as<int64_t>(), T, o[0], o[1], o[2], lshift, bits,
         keys.as<uint64_t>(), vals.as<uint32_t>(), tmp.as<float4>());
     CHS_LAUNCH_CHECK();
@@ -164,7 +168,7 @@ static chs_status plan_impl(chs_index ix, int mode, const double* xyz, const int
                            tv.as<uint32_t>(), nq, bits));
   } else {
     k_plan_keys<uint32_t><<<grid_for(nq), kThreads, 0, st>>>(
-        mode, xyz, pidx, nq, ix->pts, ix->inv_perm, ix->perm, ix->n, ix->tiles_d,
+        mode, xyz, pidx, nq, ix->pts, ix->inv_perm, ix->perm, ix->n, ix->tiles_d, tp[0],
         tp_d.as<TilePlan>(), toff_d.as<int64_t>(), T, o[0], o[1], o[2], lshift, bits,
         keys.as<uint32_t>(), vals.as<uint32_t>(), tmp.as<float4>());
     CHS_LAUNCH_CHECK();
@@ -173,12 +177,11 @@ static chs_status plan_impl(chs_index ix, int mode, const double* xyz, const int
   }
   k_plan_gather<<<grid_for(nq), kThreads, 0, st>>>(vals.as<uint32_t>(), tmp.as<float4>(), nq, q4);
   CHS_LAUNCH_CHECK();
-  // tp and toff copies were queued from host vectors that die here
-  CHS_HIP(hipStreamSynchronize(st));
+  if (T > 1) CHS_HIP(hipStreamSynchronize(st));  // tp, toff copies read host vectors
   return CHS_OK;
 }
 
-static chs_status check_queries(chs_index ix, const chs_queries* qs) {
+chs_status check_queries(chs_index ix, const chs_queries* qs) {
   if (!ix || !qs) {
     set_error("index or queries is NULL");
     return CHS_E_INVALID;
@@ -203,6 +206,49 @@ static chs_status check_queries(chs_index ix, const chs_queries* qs) {
   return CHS_OK;
 }
 
+// Processing order of "every point" queries, computed once by the build and
+// kept on the index: centres in Hilbert order, in waves of at most 64 that
+// never straddle two tiles (largest tiles first).
+chs_status plan_every_point(chs_index ix, hipStream_t st) {
+  const int T = ix->ntiles;
+  std::vector<int64_t> order(T);
+  for (int t = 0; t < T; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    return ix->tile_off[a + 1] - ix->tile_off[a] > ix->tile_off[b + 1] - ix->tile_off[b];
+  });
+  std::vector<int32_t> rank(T);
+  for (int r = 0; r < T; ++r) rank[order[r]] = r;
+  float4* a = nullptr;
+  CHS_TRY(ix->own(&a, (size_t)ix->n));
+  CHS_TRY(plan_impl(ix, 0, nullptr, nullptr, ix->n, rank, a, st));
+  if (T > 1) {
+    std::vector<int32_t> wtile, wstart, qend(T);
+    int64_t pos = 0;
+    for (int r = 0; r < T; ++r) {
+      const int t = (int)order[r];
+      const int64_t nt = ix->tile_off[t + 1] - ix->tile_off[t];
+      for (int64_t b = 0; b < nt; b += kWave) {
+        wtile.push_back(t);
+        wstart.push_back((int32_t)(pos + b));
+      }
+      pos += nt;
+      qend[t] = (int32_t)pos;
+    }
+    CHS_TRY(ix->own(&ix->wave_tile, wtile.size()));
+    CHS_TRY(ix->own(&ix->wave_start, wstart.size()));
+    CHS_TRY(ix->own(&ix->tile_qend, (size_t)T));
+    CHS_HIP(hipMemcpyAsync(ix->wave_tile, wtile.data(), 4 * wtile.size(), hipMemcpyHostToDevice, st));
+    CHS_HIP(hipMemcpyAsync(ix->wave_start, wstart.data(), 4 * wstart.size(), hipMemcpyHostToDevice, st));
+    CHS_HIP(hipMemcpyAsync(ix->tile_qend, qend.data(), 4 * (size_t)T, hipMemcpyHostToDevice, st));
+    CHS_HIP(hipStreamSynchronize(st));
+    ix->allq_waves = (int64_t)wtile.size();
+  } else {
+    ix->allq_waves = (ix->n + kWave - 1) / kWave;
+  }
+  ix->allq = a;
+  return CHS_OK;
+}
+
 chs_status plan_queries(chs_index ix, const chs_queries* qs, QueryPlan* plan, hipStream_t st) {
   plan->nq = qs->nq;
   plan->wave_tile = nullptr;
@@ -210,47 +256,7 @@ chs_status plan_queries(chs_index ix, const chs_queries* qs, QueryPlan* plan, hi
   plan->tile_qend = nullptr;
   plan->nwaves = (qs->nq + kWave - 1) / kWave;
   if (qs->nq == 0) return CHS_OK;
-  const int T = ix->ntiles;
   if (!qs->xyz && !qs->point_idx) {
-    if (!ix->allq) {
-      // cached on the index: the order of "every point" queries never changes
-      std::vector<int64_t> order(T);
-      for (int t = 0; t < T; ++t) order[t] = t;
-      std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
-        return ix->tile_off[a + 1] - ix->tile_off[a] > ix->tile_off[b + 1] - ix->tile_off[b];
-      });
-      std::vector<int32_t> rank(T);
-      for (int r = 0; r < T; ++r) rank[order[r]] = r;
-      float4* a = nullptr;
-      CHS_TRY(ix->own(&a, (size_t)ix->n));
-      CHS_TRY(plan_impl(ix, 0, nullptr, nullptr, ix->n, rank, a, st));
-      if (T > 1) {
-        // waves of at most 64 queries that stay inside one tile
-        std::vector<int32_t> wtile, wstart, qend(T);
-        int64_t pos = 0;
-        for (int r = 0; r < T; ++r) {
-          const int t = (int)order[r];
-          const int64_t nt = ix->tile_off[t + 1] - ix->tile_off[t];
-          for (int64_t b = 0; b < nt; b += kWave) {
-            wtile.push_back(t);
-            wstart.push_back((int32_t)(pos + b));
-          }
-          pos += nt;
-          qend[t] = (int32_t)pos;
-        }
-        CHS_TRY(ix->own(&ix->wave_tile, wtile.size()));
-        CHS_TRY(ix->own(&ix->wave_start, wstart.size()));
-        CHS_TRY(ix->own(&ix->tile_qend, (size_t)T));
-        CHS_HIP(hipMemcpyAsync(ix->wave_tile, wtile.data(), 4 * wtile.size(), hipMemcpyHostToDevice, st));
-        CHS_HIP(hipMemcpyAsync(ix->wave_start, wstart.data(), 4 * wstart.size(), hipMemcpyHostToDevice, st));
-        CHS_HIP(hipMemcpyAsync(ix->tile_qend, qend.data(), 4 * (size_t)T, hipMemcpyHostToDevice, st));
-        CHS_HIP(hipStreamSynchronize(st));
-        ix->allq_waves = (int64_t)wtile.size();
-      } else {
-        ix->allq_waves = (ix->n + kWave - 1) / kWave;
-      }
-      ix->allq = a;
-    }
     plan->q = ix->allq;
     plan->wave_tile = ix->wave_tile;
     plan->wave_start = ix->wave_start;
@@ -423,7 +429,8 @@ struct RadiusArgs {
   float r;
   int32_t* __restrict__ counts;         // count pass: [nq] caller order
   const int64_t* __restrict__ offsets;  // fill pass: [nq+1]
-  int32_t* __restrict__ nbr;            // fill pass
+  int32_t* __restrict__ nbr;            // fill pass: [total]
+  int64_t total;                        // fill pass: entries of nbr
 };
 
 // Fill-pass staging: each lane appends its matches to a private LDS
@@ -533,8 +540,12 @@ __device__ __forceinline__ void radius_item(const RadiusArgs& A, const Item& it,
   int nb = 0;
   int32_t* my_seg = seg_base + (FILL ? lane * Stage<ST>::stride : 0);
   if (FILL && active) {
+    // rows are clipped to nbr's extent: offsets that do not belong to these
+    // queries and this r write nothing outside [0, total)
     wpos = A.offsets[qid];
     wend = A.offsets[qid + 1];
+    if (wend > A.total) wend = A.total;
+    if (wpos < 0 || wpos > wend) wpos = wend = 0;
   }
   if (tb.any) {
     const VBox bx = voxel_box<KS>(g, tb.lo, tb.hi, pad);
@@ -1090,16 +1101,18 @@ static Waves make_waves(chs_index ix, const QueryPlan& plan, int32_t* counter) {
 // and by the persistent option; a plain index uses the lighter kernels
 static bool multi(chs_index ix) { return ix->ntiles > 1 || ix->persistent; }
 
-static chs_status launch_dims(chs_index ix, const QueryPlan& plan, hipStream_t st,
+// ctr: the call's own work counter (persistent launches), so that searches
+// in flight on different streams never share one.
+static chs_status launch_dims(chs_index ix, const QueryPlan& plan, hipStream_t st, Buf* ctr,
                               int32_t** counter, unsigned* nblocks) {
   const int64_t nb = (plan.nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
   *counter = nullptr;
   *nblocks = (unsigned)(nb > 0 ? nb : 1);
   if (ix->persistent) {
-    if (!ix->work_counter) CHS_TRY(ix->own(&ix->work_counter, 1));
-    k_reset_counter<<<1, kWave, 0, st>>>(ix->work_counter);
+    CHS_TRY(ctr->alloc(sizeof(int32_t)));
+    k_reset_counter<<<1, kWave, 0, st>>>(ctr->as<int32_t>());
     CHS_LAUNCH_CHECK();
-    *counter = ix->work_counter;
+    *counter = ctr->as<int32_t>();
     const int64_t cap = 256 * 8;
     *nblocks = (unsigned)(nb < cap ? (nb > 0 ? nb : 1) : cap);
   }
@@ -1139,7 +1152,15 @@ template <bool FILL>
 static void launch_radius(chs_index ix, unsigned nb, hipStream_t st, const RadiusArgs& A,
                           int32_t kernel, int64_t mean_rows = 0) {
   if constexpr (FILL) {
-    if (mean_rows >= kLongRows) {
+    if (ix->fill_stage == kStageShort) {
+      launch_radius_st<FILL, kStageShort>(ix, nb, st, A, kernel);
+      return;
+    }
+    if (ix->fill_stage == kStageMid) {
+      launch_radius_st<FILL, kStageMid>(ix, nb, st, A, kernel);
+      return;
+    }
+    if (mean_rows >= kLongRows || ix->fill_stage == kStageLong) {
       launch_radius_st<FILL, kStageLong>(ix, nb, st, A, kernel);
       return;
     }
@@ -1183,11 +1204,12 @@ static chs_status radius_count_impl(chs_index ix, const QueryPlan& plan, int32_t
   Buf counts(&al);
   CHS_TRY(counts.alloc(sizeof(int32_t) * (nq > 0 ? nq : 1)));
   if (nq > 0) {
+    Buf cbuf(&al);
     int32_t* ctr;
     unsigned nb;
-    CHS_TRY(launch_dims(ix, plan, st, &ctr, &nb));
+    CHS_TRY(launch_dims(ix, plan, st, &cbuf, &ctr, &nb));
     RadiusArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), r,
-                 counts.as<int32_t>(), nullptr, nullptr};
+                 counts.as<int32_t>(), nullptr, nullptr, 0};
     launch_radius<false>(ix, nb, st, A, kernel);
     CHS_LAUNCH_CHECK();
   }
@@ -1199,11 +1221,14 @@ static chs_status radius_fill_impl(chs_index ix, const QueryPlan& plan, int32_t 
                                    const int64_t* offsets, int32_t* nbr, int64_t total,
                                    hipStream_t st) {
   if (plan.nq == 0) return CHS_OK;
+  Alloc al = ix->al;
+  al.stream = st;
+  Buf cbuf(&al);
   int32_t* ctr;
   unsigned nb;
-  CHS_TRY(launch_dims(ix, plan, st, &ctr, &nb));
+  CHS_TRY(launch_dims(ix, plan, st, &cbuf, &ctr, &nb));
   RadiusArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), r, nullptr,
-               offsets, nbr};
+               offsets, nbr, total};
   launch_radius<true>(ix, nb, st, A, kernel, total / plan.nq);
   CHS_LAUNCH_CHECK();
   return CHS_OK;
@@ -1225,9 +1250,46 @@ static chs_status check_kernel(int32_t kernel) {
   return CHS_OK;
 }
 
+chs_status knn_impl(chs_index ix, const chs_queries* qs, int32_t k, float r_max,
+                           int32_t* idx, float* d2, const Alloc& al, hipStream_t st) {
+  CHS_TRY(check_queries(ix, qs));
+  if (k < 1 || k > 64) {
+    set_error("k = %d outside [1, 64]", k);
+    return CHS_E_INVALID;
+  }
+  if (std::isnan(r_max) || r_max < 0.0f) {
+    set_error("r_max must be >= 0 or +inf");
+    return CHS_E_INVALID;
+  }
+  if (qs->nq > 0 && (!idx || !d2)) {
+    set_error("idx or d2 is NULL");
+    return CHS_E_INVALID;
+  }
+  if (qs->nq == 0) return CHS_OK;
+  QueryPlan plan(&al);
+  CHS_TRY(plan_queries(ix, qs, &plan, st));
+  const float rmax2 = std::isinf(r_max) ? INFINITY : r_max * r_max;
+  Buf cbuf(&al);
+  int32_t* ctr;
+  unsigned nb;
+  CHS_TRY(launch_dims(ix, plan, st, &cbuf, &ctr, &nb));
+  KnnArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), k, rmax2, idx, d2};
+  if (k <= 8)
+    launch_knn<8>(ix, nb, st, A);
+  else if (k <= 16)
+    launch_knn<16>(ix, nb, st, A);
+  else if (k <= 32)
+    launch_knn<32>(ix, nb, st, A);
+  else
+    launch_knn<64>(ix, nb, st, A);
+  CHS_LAUNCH_CHECK();
+  return CHS_OK;
+}
+
 }  // namespace chs
 
 using namespace chs;
+
 
 extern "C" chs_status chs_kernel_count(chs_index ix, const chs_queries* qs, int32_t kernel,
                                        float r, int64_t* offsets, int64_t* total, hipStream_t st) {
@@ -1337,37 +1399,11 @@ extern "C" chs_status chs_radius_search(chs_index ix, const chs_queries* qs, flo
 extern "C" chs_status chs_knn(chs_index ix, const chs_queries* qs, int32_t k, float r_max,
                               int32_t* idx, float* d2, hipStream_t st) {
   clear_error();
-  CHS_TRY(check_queries(ix, qs));
-  if (k < 1 || k > 64) {
-    set_error("k = %d outside [1, 64]", k);
+  if (!ix) {
+    set_error("index is NULL");
     return CHS_E_INVALID;
   }
-  if (std::isnan(r_max) || r_max < 0.0f) {
-    set_error("r_max must be >= 0 or +inf");
-    return CHS_E_INVALID;
-  }
-  if (qs->nq > 0 && (!idx || !d2)) {
-    set_error("idx or d2 is NULL");
-    return CHS_E_INVALID;
-  }
-  if (qs->nq == 0) return CHS_OK;
   Alloc al = ix->al;
   al.stream = st;
-  QueryPlan plan(&al);
-  CHS_TRY(plan_queries(ix, qs, &plan, st));
-  const float rmax2 = std::isinf(r_max) ? INFINITY : r_max * r_max;
-  int32_t* ctr;
-  unsigned nb;
-  CHS_TRY(launch_dims(ix, plan, st, &ctr, &nb));
-  KnnArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), k, rmax2, idx, d2};
-  if (k <= 8)
-    launch_knn<8>(ix, nb, st, A);
-  else if (k <= 16)
-    launch_knn<16>(ix, nb, st, A);
-  else if (k <= 32)
-    launch_knn<32>(ix, nb, st, A);
-  else
-    launch_knn<64>(ix, nb, st, A);
-  CHS_LAUNCH_CHECK();
-  return CHS_OK;
+  return knn_impl(ix, qs, k, r_max, idx, d2, al, st);
 }

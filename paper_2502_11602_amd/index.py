@@ -2,6 +2,7 @@
 C ABI of libchs.so.  PyTorch provides device memory, streams and (for the
 aggregation) autograd glue; the index, the searches and their results are
 computed by the library's HIP kernels."""
+import contextlib
 import ctypes
 import math
 
@@ -16,9 +17,23 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+@contextlib.contextmanager
+def _on(device, stream=None):
+    """Make `device` and `stream` current for a library call: the allocator
+    then hands out (and takes back) temporaries on the stream the call's
+    kernels run on."""
+    with torch.cuda.device(device):
+        if stream is None:
+            yield
+        else:
+            with torch.cuda.stream(stream):
+                yield
+
+
 class TorchAllocator:
     """chs_allocator backed by PyTorch's caching allocator on the current
-    stream, so library temporaries and index memory are stream-ordered."""
+    stream, so library temporaries and index memory are stream-ordered (the
+    methods below make the call's stream current around every call)."""
 
     def __init__(self, device):
         self.device = device
@@ -99,7 +114,8 @@ class GridIndex:
         h = ctypes.c_void_p()
         self._h = None
         self.ntiles = 1
-        with torch.cuda.device(self.device):
+        self._build_stream = stream
+        with _on(self.device, stream):
             if tile_off is None:
                 p = _params(cell, dims, flavor, mixed_dense_pct, max_dense_cells)
                 st = lib().chs_build(xyz.data_ptr(), xyz.shape[0], ctypes.byref(p),
@@ -141,9 +157,23 @@ class GridIndex:
         return dict(origin=list(inf.origin), max32=list(inf.max32), cell=list(inf.cell),
                     ncell=list(inf.ncell), n_points=inf.n_points, dims=inf.dims)
 
+    def set_fill_stage(self, entries=0):
+        """LDS entries per query of the radius fill (16, 24, 32; 0 = by the
+        mean row length); results are identical."""
+        check(lib().chs_index_set_option(self._h, 5, int(entries)), "chs_index_set_option")
+
+    def coords(self, stream=None):
+        """The index's FP32 coordinates in input order ([n,3] float32): the
+        library's recentring fl32(p - p-) (each tile in its own frame)."""
+        out = torch.empty((self.n, 3), dtype=torch.float32, device=self.device)
+        with _on(self.device, stream):
+            check(lib().chs_index_coords(self._h, out.data_ptr(), _stream(stream)),
+                  "chs_index_coords")
+        return out
+
     def close(self):
         if getattr(self, "_h", None):
-            with torch.cuda.device(self.device):
+            with _on(self.device, self._build_stream):
                 lib().chs_free(self._h)
             self._h = None
 
@@ -190,17 +220,30 @@ class GridIndex:
         q, nq, keep = _queries(queries, self.n)
         off = torch.empty(nq + 1, dtype=torch.int64, device=self.device)
         tot = ctypes.c_int64(0)
-        with torch.cuda.device(self.device):
+        with _on(self.device, stream):
             check(lib().chs_kernel_count(self._h, ctypes.byref(q), self.KERNELS[kernel],
                                          ctypes.c_float(r), off.data_ptr(), ctypes.byref(tot),
                                          _stream(stream)), "chs_kernel_count")
         return off, tot.value
 
     def radius_fill(self, r, offsets, total, queries=None, out=None, stream=None, kernel="sphere"):
+        """Fill pass into ``out`` (int32, at least ``total`` entries) or a new
+        tensor; ``offsets`` as returned by radius_count."""
         q, nq, keep = _queries(queries, self.n)
-        nbr = out if out is not None else torch.empty(max(total, 0), dtype=torch.int32,
+        total = int(total)
+        if not (isinstance(offsets, torch.Tensor) and offsets.dtype == torch.int64
+                and offsets.shape == (nq + 1,) and offsets.device == self.device
+                and offsets.is_contiguous()):
+            raise ValueError(f"offsets must be a contiguous int64 [{nq + 1}] tensor on {self.device}")
+        if total < 0:
+            raise ValueError("total must be >= 0")
+        if out is not None and not (out.dtype == torch.int32 and out.device == self.device
+                                    and out.is_contiguous() and out.numel() >= total):
+            raise ValueError(f"out must be a contiguous int32 tensor on {self.device} "
+                             f"with at least {total} entries")
+        nbr = out if out is not None else torch.empty(total, dtype=torch.int32,
                                                       device=self.device)
-        with torch.cuda.device(self.device):
+        with _on(self.device, stream):
             check(lib().chs_kernel_fill(self._h, ctypes.byref(q), self.KERNELS[kernel],
                                         ctypes.c_float(r), offsets.data_ptr(),
                                         nbr.data_ptr() if total else None, total,
@@ -223,7 +266,7 @@ class GridIndex:
         if idx.shape != (nq, k) or d2.shape != (nq, k) or idx.dtype != torch.int32 \
                 or d2.dtype != torch.float32 or not (idx.is_contiguous() and d2.is_contiguous()):
             raise ValueError("idx / d2 must be contiguous [nq,k] int32 / float32")
-        with torch.cuda.device(self.device):
+        with _on(self.device, stream):
             check(lib().chs_knn(self._h, ctypes.byref(q), k, ctypes.c_float(r_max),
                                 idx.data_ptr() if nq else None, d2.data_ptr() if nq else None,
                                 _stream(stream)), "chs_knn")
@@ -235,7 +278,7 @@ class GridIndex:
         q, nq, keep = _queries(queries, self.n)
         idx = torch.empty((nq, k), dtype=torch.int32, device=self.device)
         d2 = torch.empty((nq, k), dtype=torch.float32, device=self.device)
-        with torch.cuda.device(self.device):
+        with _on(self.device, stream):
             check(lib().chs_knn(self._h, ctypes.byref(q), k, ctypes.c_float(r_max),
                                 idx.data_ptr() if nq else None, d2.data_ptr() if nq else None,
                                 _stream(stream)), "chs_knn")

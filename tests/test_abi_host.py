@@ -98,3 +98,23 @@ def test_2d_cell_z_ignored(L):
     p = _params(dims=2, cell=(1.0, 1.0, 0.0))
     st = L.chs_build(None, 10, ctypes.byref(p), None, None, ctypes.byref(h))
     assert st == 1 and b"NULL" in L.chs_last_error()
+
+
+def test_agg_rejects_pair_slots_beyond_int32(L):
+    # the backward regroups Q*K pair slots (plus Q centre slots) with int32
+    # positions: Q*(K+1) must stay below 2^31
+    Q, K = 40_000_000, 53  # Q*(K+1) = 2.16e9 > 2^31 - 1
+    st = L.chs_gauss_agg_fwd(FAKE, FAKE, FAKE, 1000, Q, K, FAKE, 8, 0.25, 0, 0, FAKE, None)
+    assert st == 1 and b"sizes" in L.chs_last_error()
+    st = L.chs_gauss_agg_bwd(FAKE, FAKE, FAKE, 1000, Q, K, FAKE, 8, 0.25, 0, 0, FAKE, FAKE, FAKE,
+                             None, None)
+    assert st == 1 and b"sizes" in L.chs_last_error()
+
+
+def test_coords_reject_null(L):
+    assert L.chs_index_coords(None, FAKE, None) == 1
+    assert b"NULL" in L.chs_last_error()
+
+
+def test_set_option_rejects_bad_values(L):
+    assert L.chs_index_set_option(None, 5, 16) == 1

@@ -33,7 +33,7 @@ def _case(n, nq, channels, seed=4, k=64, r_max=0.5):
     ix = GridIndex(x64, cell=0.5)
     q = torch.from_numpy(c["queries"]).to(dev)
     nbr = neighbour_lists(ix, q, k=k, r_max=r_max)
-    x32 = recentred(x64, ix)
+    x32 = recentred(ix)
     return c, x32, q, nbr
 
 

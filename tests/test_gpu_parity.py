@@ -473,3 +473,71 @@ def test_config2_full_size_sampled(config2_oracle, flavor):
     st = torch.from_numpy(sel.astype(np.int64)).to(dev)
     np.testing.assert_array_equal(idx[st].cpu().numpy(), oi)
     np.testing.assert_array_equal(d2[st].cpu().numpy(), od)
+
+
+# ---------------------------------------------------------------- every query at full size
+@pytest.fixture(scope="module")
+def config1_cloud():
+    return cloudgen.config1()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
+def test_config1_every_query_digests(config1_cloud, flavor):
+    """The 10 M-point ALS tile, every point a query, in the launch
+    configuration the benchmark times: every query's neighbour count and
+    order-independent neighbour hash (sphere at 0.5-4 m, cube and cylinder at
+    2 and 3 m: fills with 16-, 24- and 32-entry stages), and every k-NN row
+    (k = 8, 16, 32) in order, summarised per block of 2^18 queries, equal the
+    oracle's digests written by tests/golden/make_config1_digests.py."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import _digest as D
+    from tests.conftest import ROOT
+    dev = _dev()
+    meta, sets = D.read_golden(os.path.join(ROOT, "tests", "golden", "config1_digests.txt"))
+    xyz = config1_cloud["xyz"]
+    assert D.fingerprint(xyz) == meta["input"][0], "the generator no longer gives the digested cloud"
+    assert int(meta["block"][0]) == D.BLOCK
+    gi = _gi()(torch.from_numpy(xyz).to(dev), cell=1.0, flavor=flavor)
+    for name, want in sets.items():
+        if name.startswith("knn_"):
+            idx, d2 = gi.knn(int(name[4:]))
+            cnt, h = D.row_hash_knn_t(idx, d2)
+            del idx, d2
+        else:
+            kern, r = name.split("_")
+            off, nbr = gi.radius(float(r), kernel=kern)
+            cnt, h = D.row_hash_csr_t(off, nbr)
+            del off, nbr
+        got = D.block_digests_t(cnt, h)
+        bad = [w[0] for g, w in zip(got, want) if g != w]
+        assert len(got) == len(want) and not bad, f"{flavor} {name}: blocks {bad[:10]} differ"
+
+
+# ---------------------------------------------------------------- every fill stage
+@pytest.mark.parametrize("stage", [16, 24, 32])
+@pytest.mark.parametrize("kernel", ["sphere", "cube", "cylinder"])
+@pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
+def test_fill_stages(stage, kernel, flavor):
+    """Each LDS stage size of the radius fill (16, 24, 32 entries per query,
+    forced with CHS_OPT_FILL_STAGE) with each kernel and flavor: config 0 at
+    r = 2.5 m (rows of tens of entries, several flushes per wave) and the
+    duplicate-heavy walls cloud, all points, against the oracle."""
+    dev = _dev()
+    c = cloudgen.config0()
+    gi = _gi()(torch.from_numpy(c["xyz"]).to(dev), cell=c["cell"], flavor=flavor)
+    gi.set_fill_stage(stage)
+    ox = oracle.OracleIndex(c["xyz"], c["cell"], flavor=flavor)
+    q = c["queries"]
+    off, nbr = gi.radius(2.5, torch.from_numpy(q).to(dev), kernel=kernel)
+    ooff, onbr = ox.radius(2.5, pidx=q, nthreads=8, kernel=kernel)
+    assert np.diff(ooff).max() > 2 * stage
+    _assert_csr_equal(off, nbr, ooff, onbr)
+    w = _walls(7)
+    gw = _gi()(torch.from_numpy(w).to(dev), cell=0.5, flavor=flavor)
+    gw.set_fill_stage(stage)
+    off, nbr = gw.radius(1.2, kernel=kernel)
+    ooff, onbr = oracle.OracleIndex(w, 0.5, flavor=flavor).radius(1.2, nthreads=8, kernel=kernel)
+    _assert_csr_equal(off, nbr, ooff, onbr)
