@@ -28,7 +28,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "radius/k-NN queries per sec at 1 GPU; achieved HBM GB/s vs peak; build Mpts/s"
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ["paper_2502_11602_amd/csrc/search.hip", "paper_2502_11602_amd/csrc/common.h"]
+KERNEL_SOURCES = ["paper_2502_11602_amd/csrc/radius.hip", "paper_2502_11602_amd/csrc/search_common.h",
+                  "paper_2502_11602_amd/csrc/common.h"]
 
 
 def code_text(src):

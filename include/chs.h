@@ -168,10 +168,18 @@ chs_status chs_tile_info(chs_index index, int32_t tile, chs_index_info_t* out /*
  * matches in on-chip memory (LDS) before writing them out, 16, 24 or 32
  * entries per query; 0 picks the size from the mean row length total / nq.
  * Results are identical. */
+/* CHS_OPT_RADIUS_SCHEDULE (default 0): how the kernel-based searches share
+ * work.  1 = tiles: a wave takes 64 nearby queries and tests every point of
+ * their common voxel box against all of them; 2 = groups: a wave takes 8
+ * nearby queries at a time and tests the points of their own, smaller
+ * common box.  0 picks groups for spheres and cubes with r >= 1.5 voxel
+ * edges, tiles otherwise.  Results are identical (the fill stage applies to
+ * tiles). */
 typedef enum chs_option {
   CHS_OPT_PERSISTENT = 1,
   CHS_OPT_KNN_SCHEDULE = 4,
-  CHS_OPT_FILL_STAGE = 5
+  CHS_OPT_FILL_STAGE = 5,
+  CHS_OPT_RADIUS_SCHEDULE = 6
 } chs_option;
 chs_status chs_index_set_option(chs_index index, int32_t option, int64_t value);
 

@@ -523,6 +523,12 @@ static chs_status build_impl(chs_index ix, const double* xyz, int64_t n, const i
     koff += (uint64_t)g.n[0] * (uint64_t)g.n[1] * (uint64_t)g.n[2];
   }
   ix->total_cells = koff;
+  double wsum = 0.0;
+  for (int t = 0; t < ntiles; ++t) {
+    const Grid& g = ix->tiles[t];
+    wsum += (double)(toff[t + 1] - toff[t]) * (g.s[0] < g.s[1] ? g.s[0] : g.s[1]);
+  }
+  ix->cell_xy = wsum / (double)toff[ntiles];
   if (ix->flavor == CHS_DENSE && ix->total_cells > (uint64_t)ix->ncells_limit()) {
     set_error("dense grid of %llu voxels exceeds the limit %lld; use the sparse or mixed flavor",
               (unsigned long long)ix->total_cells, (long long)ix->ncells_limit());
@@ -661,6 +667,14 @@ extern "C" chs_status chs_index_set_option(chs_index ix, int32_t option, int64_t
       return CHS_E_INVALID;
     }
     ix->fill_stage = (int32_t)value;
+    return CHS_OK;
+  }
+  if (option == CHS_OPT_RADIUS_SCHEDULE) {
+    if (value < 0 || value > 2) {
+      set_error("radius schedule must be 0 (auto), 1 (64-query tiles) or 2 (8-query groups)");
+      return CHS_E_INVALID;
+    }
+    ix->radius_sched = (int32_t)value;
     return CHS_OK;
   }
   if (option == CHS_OPT_KNN_SCHEDULE) {

@@ -115,6 +115,8 @@ struct chs_index_s {
   bool persistent = false;  // searches pull waves from a work counter
   bool knn_density = false;  // k-NN with the density-growth schedule of Alg. 2
   int32_t fill_stage = 0;    // radius fill: LDS entries per lane (0: by mean row length)
+  int32_t radius_sched = 0;  // radius schedule: 0 auto, 1 64-query tiles, 2 8-query groups
+  double cell_xy = 1.0;      // point-weighted mean of the tiles' smaller xy voxel edge
   // per tile, host copies (tile 0 is the whole cloud of a plain index)
   std::vector<chs::Grid> tiles;
   std::vector<double> origin;   // [3 * ntiles]

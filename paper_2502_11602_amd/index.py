@@ -157,6 +157,13 @@ class GridIndex:
         return dict(origin=list(inf.origin), max32=list(inf.max32), cell=list(inf.cell),
                     ncell=list(inf.ncell), n_points=inf.n_points, dims=inf.dims)
 
+    def set_radius_schedule(self, schedule="auto"):
+        """Work sharing of the kernel-based searches: "tiles" (64 queries
+        per union box), "groups" (8 queries per box) or "auto"; results are
+        identical."""
+        check(lib().chs_index_set_option(self._h, 6, {"auto": 0, "tiles": 1, "groups": 2}[schedule]),
+              "chs_index_set_option")
+
     def set_fill_stage(self, entries=0):
         """LDS entries per query of the radius fill (16, 24, 32; 0 = by the
         mean row length); results are identical."""

@@ -132,13 +132,15 @@ def test_radius_config0(flavor, r):
     _assert_csr_equal(off, nbr, ooff, onbr)
 
 
+@pytest.mark.parametrize("sched", ["tiles", "groups"])
 @pytest.mark.parametrize("name", sorted(CLOUDS))
 @pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
 @pytest.mark.parametrize("dims,s", [(3, 1.0), (3, 0.3), (2, 2.5)])
-def test_radius_all_points(name, flavor, dims, s):
+def test_radius_all_points(name, flavor, dims, s, sched):
     dev = _dev()
     xyz = CLOUDS[name](4)
     gi = _gi()(torch.from_numpy(xyz).to(dev), cell=s, dims=dims, flavor=flavor)
+    gi.set_radius_schedule(sched)
     ox = oracle.OracleIndex(xyz, s, dims=dims, flavor=flavor)
     r = 0.7 if name != "blob" else 0.05
     off, nbr = gi.radius(r)
@@ -146,14 +148,16 @@ def test_radius_all_points(name, flavor, dims, s):
     _assert_csr_equal(off, nbr, ooff, onbr)
 
 
+@pytest.mark.parametrize("sched", ["tiles", "groups"])
 @pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
-def test_radius_coordinate_queries(flavor):
+def test_radius_coordinate_queries(flavor, sched):
     dev = _dev()
     xyz = cloudgen.small_als(8, 40_000)
     rng = np.random.default_rng(11)
     qa = rng.uniform(xyz.min(0) - 4.0, xyz.max(0) + 4.0, (5000, 3))
     qa[:50] = xyz[:50]  # exactly on cloud points
     gi = _gi()(torch.from_numpy(xyz).to(dev), cell=1.0, flavor=flavor)
+    gi.set_radius_schedule(sched)
     ox = oracle.OracleIndex(xyz, 1.0, flavor=flavor)
     for r in (0.6, 3.0):
         off, nbr = gi.radius(r, torch.from_numpy(qa).to(dev))
@@ -209,14 +213,16 @@ def test_other_kernels_config0(kernel, flavor):
     _assert_csr_equal(off, nbr, ooff, onbr)
 
 
+@pytest.mark.parametrize("sched", ["tiles", "groups"])
 @pytest.mark.parametrize("kernel", ["cube", "cylinder"])
 @pytest.mark.parametrize("name", sorted(CLOUDS))
 @pytest.mark.parametrize("dims,s", [(3, 0.3), (2, 2.5)])
-def test_other_kernels_all_points(kernel, name, dims, s):
+def test_other_kernels_all_points(kernel, name, dims, s, sched):
     dev = _dev()
     xyz = CLOUDS[name](4)
     for flavor in ("dense", "sparse", "mixed"):
         gi = _gi()(torch.from_numpy(xyz).to(dev), cell=s, dims=dims, flavor=flavor)
+        gi.set_radius_schedule(sched)
         ox = oracle.OracleIndex(xyz, s, dims=dims, flavor=flavor)
         r = 0.7 if name != "blob" else 0.05
         off, nbr = gi.radius(r, kernel=kernel)
@@ -521,13 +527,15 @@ def test_config1_every_query_digests(config1_cloud, flavor):
 @pytest.mark.parametrize("kernel", ["sphere", "cube", "cylinder"])
 @pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
 def test_fill_stages(stage, kernel, flavor):
-    """Each LDS stage size of the radius fill (16, 24, 32 entries per query,
-    forced with CHS_OPT_FILL_STAGE) with each kernel and flavor: config 0 at
-    r = 2.5 m (rows of tens of entries, several flushes per wave) and the
-    duplicate-heavy walls cloud, all points, against the oracle."""
+    """Each LDS stage size of the 64-query tiles' radius fill (16, 24, 32
+    entries per query, forced with CHS_OPT_FILL_STAGE) with each kernel and
+    flavor: config 0 at r = 2.5 m (rows of tens of entries, several flushes
+    per wave) and the duplicate-heavy walls cloud, all points, against the
+    oracle."""
     dev = _dev()
     c = cloudgen.config0()
     gi = _gi()(torch.from_numpy(c["xyz"]).to(dev), cell=c["cell"], flavor=flavor)
+    gi.set_radius_schedule("tiles")
     gi.set_fill_stage(stage)
     ox = oracle.OracleIndex(c["xyz"], c["cell"], flavor=flavor)
     q = c["queries"]
@@ -537,7 +545,33 @@ def test_fill_stages(stage, kernel, flavor):
     _assert_csr_equal(off, nbr, ooff, onbr)
     w = _walls(7)
     gw = _gi()(torch.from_numpy(w).to(dev), cell=0.5, flavor=flavor)
+    gw.set_radius_schedule("tiles")
     gw.set_fill_stage(stage)
+    off, nbr = gw.radius(1.2, kernel=kernel)
+    ooff, onbr = oracle.OracleIndex(w, 0.5, flavor=flavor).radius(1.2, nthreads=8, kernel=kernel)
+    _assert_csr_equal(off, nbr, ooff, onbr)
+
+
+@pytest.mark.parametrize("kernel", ["sphere", "cube", "cylinder"])
+@pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
+def test_query_groups(kernel, flavor):
+    """The 8-query-group schedule (CHS_OPT_RADIUS_SCHEDULE = 2) with each
+    kernel and flavor: config 0 at r = 0.5, 2.5 and 6 m (packed lists of a
+    few to several thousand candidates, so more than one LDS piece), the
+    walls cloud (duplicates, points on voxel walls), against the oracle."""
+    dev = _dev()
+    c = cloudgen.config0()
+    gi = _gi()(torch.from_numpy(c["xyz"]).to(dev), cell=c["cell"], flavor=flavor)
+    gi.set_radius_schedule("groups")
+    ox = oracle.OracleIndex(c["xyz"], c["cell"], flavor=flavor)
+    q = c["queries"]
+    for r in (0.5, 2.5, 6.0):
+        off, nbr = gi.radius(r, torch.from_numpy(q).to(dev), kernel=kernel)
+        ooff, onbr = ox.radius(r, pidx=q, nthreads=8, kernel=kernel)
+        _assert_csr_equal(off, nbr, ooff, onbr)
+    w = _walls(8)
+    gw = _gi()(torch.from_numpy(w).to(dev), cell=0.5, flavor=flavor)
+    gw.set_radius_schedule("groups")
     off, nbr = gw.radius(1.2, kernel=kernel)
     ooff, onbr = oracle.OracleIndex(w, 0.5, flavor=flavor).radius(1.2, nthreads=8, kernel=kernel)
     _assert_csr_equal(off, nbr, ooff, onbr)
