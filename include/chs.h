@@ -276,6 +276,20 @@ chs_status chs_kernel_search(chs_index index, const chs_queries* queries, int32_
 chs_status chs_knn(chs_index index, const chs_queries* queries, int32_t k, float r_max,
                    int32_t* idx, float* d2, hipStream_t stream);
 
+/* chs_knn for callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, results and errors as chs_knn, but no allocator is called.
+ * Every temporary (the query plan with its sort buffers, the persistent work
+ * counter) is carved from a fixed 32 MiB device array that the library holds
+ * on each GPU it runs on until the process ends.  Index or coordinate
+ * queries: nq <= 2^19 (CHS_E_CAPACITY beyond, checked before any device
+ * work); "every point" queries use the order the build planned, any n.  Call
+ * with the index's device current.  All calls on one GPU share that GPU's
+ * array: two calls in flight at once (on different streams or threads) race
+ * and give wrong results.  Does not synchronise. */
+chs_status chs_knn_noalloc(chs_index index, const chs_queries* queries, int32_t k, float r_max,
+                           int32_t* idx, float* d2, hipStream_t stream);
+
 /* ---- Gaussian-weighted neighbourhood aggregation (a project addition) ----
  * out[q,c] = sum_t w_qt f[j_t, c] with w_qt = exp(-D(x_j, x_q) / (2 sigma^2)),
  * x_q = x[qidx[q]], j_t = nbr[q,t]; negative or out-of-range entries of nbr

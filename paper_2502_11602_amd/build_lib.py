@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["prims.hip", "build.hip", "search.hip", "radius.hip", "knn.hip", "agg.hip"]
+SOURCES = ["prims.hip", "build.hip", "search.hip", "radius.hip", "knn.hip", "agg.hip", "noalloc.hip"]
 LIB = os.path.join(HERE, "libchs.so")
 ARCH = os.environ.get("CHS_OFFLOAD_ARCH", "gfx950")
 

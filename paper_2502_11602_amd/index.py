@@ -279,6 +279,21 @@ class GridIndex:
                                 _stream(stream)), "chs_knn")
         return idx, d2
 
+    def knn_noalloc(self, k, idx, d2, queries=None, r_max=math.inf, stream=None):
+        """k-NN into preallocated idx / d2 through chs_knn_noalloc: the library
+        allocates nothing (its temporaries live in a fixed device array shared
+        by every such call on the GPU; calls must not overlap)."""
+        q, nq, keep = _queries(queries, self.n)
+        if idx.shape != (nq, k) or d2.shape != (nq, k) or idx.dtype != torch.int32 \
+                or d2.dtype != torch.float32 or not (idx.is_contiguous() and d2.is_contiguous()):
+            raise ValueError("idx / d2 must be contiguous [nq,k] int32 / float32")
+        with _on(self.device, stream):
+            check(lib().chs_knn_noalloc(self._h, ctypes.byref(q), k, ctypes.c_float(r_max),
+                                        idx.data_ptr() if nq else None,
+                                        d2.data_ptr() if nq else None, _stream(stream)),
+                  "chs_knn_noalloc")
+        return idx, d2
+
     def knn(self, k, queries=None, r_max=math.inf, stream=None):
         """(idx int32 [nq,k], d2 float32 [nq,k]) sorted by (d2, index);
         missing entries are (-1, +inf)."""
