@@ -370,22 +370,35 @@ __device__ __forceinline__ void radius_group_item(const RadiusArgs& A, const Ite
     float qx[kQGroup], qy[kQGroup], qz[kQGroup];
     bool qa[kQGroup];
     int32_t cnt[kQGroup];
-    global_i32 row[kQGroup];
-    int32_t room[kQGroup];
+    global_i32 row[kQGroup];   // fill: the query's row
+    int32_t rlen[kQGroup];     //   its length (clipped to nbr)
+    int32_t wcnt[kQGroup];     //   entries found so far
 #pragma unroll
     for (int j = 0; j < kQGroup; ++j) {
       qa[j] = false;
-      qx[j] = qy[j] = qz[j] = 0.f;
+      // a query without a valid centre gets NaN coordinates: every test
+      // fails and it takes no further work
+      qx[j] = qy[j] = qz[j] = __builtin_nanf("");
       cnt[j] = 0;
       row[j] = (global_i32)A.nbr;
-      room[j] = 0;
+      rlen[j] = 0;
+      wcnt[j] = 0;
       if (j < ng) {
         const float4 c = load_const(cq, (int32_t)(g0 + j));
         const uint32_t w = __float_as_uint(c.w);
         qa[j] = !(w & kInactive) && (int64_t)w < A.W.nq;
-        qx[j] = c.x;
-        qy[j] = c.y;
-        qz[j] = c.z;
+        if (qa[j]) {
+          qx[j] = c.x;
+          qy[j] = c.y;
+          qz[j] = c.z;
+        }
+        if (FILL) {
+          // the fill keeps the centres in vector registers (same value in
+          // every lane), leaving the scalar registers to the row cursors
+          asm volatile("v_mov_b32 %0, %1" : "=v"(qx[j]) : "s"(qx[j]));
+          asm volatile("v_mov_b32 %0, %1" : "=v"(qy[j]) : "s"(qy[j]));
+          asm volatile("v_mov_b32 %0, %1" : "=v"(qz[j]) : "s"(qz[j]));
+        }
         if (FILL && qa[j]) {
           // rows are clipped to nbr's extent: offsets that do not belong to
           // these queries and this r write nothing outside [0, total); a
@@ -395,7 +408,7 @@ __device__ __forceinline__ void radius_group_item(const RadiusArgs& A, const Ite
           if (re > A.total) re = A.total;
           if (rb < 0 || rb > re) rb = re = 0;
           row[j] = (global_i32)A.nbr + rb;
-          room[j] = re - rb > (int64_t)INT32_MAX ? INT32_MAX : (int32_t)(re - rb);
+          rlen[j] = re - rb > (int64_t)INT32_MAX ? INT32_MAX : (int32_t)(re - rb);
         }
       }
     }
@@ -453,18 +466,20 @@ __device__ __forceinline__ void radius_group_item(const RadiusArgs& A, const Ite
           const int32_t pid = __float_as_int(P.w) - poff;
 #pragma unroll
           for (int j = 0; j < kQGroup; ++j) {
-            if (!qa[j]) continue;
+            if (j >= ng) break;
             const bool hit = inside<KS>(make_float4(qx[j], qy[j], qz[j], 0.f), P, rr, R);
             const uint64_t m = __ballot(hit) & vmask;
             if (!FILL) {
               cnt[j] += __popcll(m);
             } else if (m) {
-              const int32_t rk = lane_rank(m);
-              if (hit && valid && rk < room[j]) row[j][(uint32_t)rk] = pid;
-              const int32_t nm = __popcll(m);
-              const int32_t wr = nm < room[j] ? nm : room[j];
-              row[j] += wr;
-              room[j] -= wr;
+              // the row cursor moves first (uniform, scalar registers), then
+              // the matching lanes store at their rank in the row, if the row
+              // has room
+              const int32_t w0 = wcnt[j];
+              wcnt[j] = w0 + __popcll(m);
+              const int32_t at = (int32_t)__builtin_amdgcn_mbcnt_hi(
+                  (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)w0));
+              if (hit && valid && at < rlen[j]) row[j][(uint32_t)at] = pid;
             }
           }
         }
