@@ -50,10 +50,10 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def counter_traffic(kernel, radius):
-    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 PMC
-    summary, or None when there is none or the kernel sources changed since
-    the counters were taken."""
+def counter_traffic(radius):
+    """HBM bytes per launch of the radius fill at ``radius`` from the
+    committed rocprofv3 PMC summary, or None when there is none or the kernel
+    sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "radius_fill_als10m_pmc.json")
     if not os.path.exists(path):
         return None
@@ -64,8 +64,7 @@ def counter_traffic(kernel, radius):
         return None
     if d.get("source_hash") != source_hash():
         return None
-    ent = d.get("per_launch_bytes", {}).get(f"{kernel}@r={radius}")
-    return ent
+    return d.get("per_launch_bytes", {}).get(f"fill@r={radius}")
 
 
 # rocprofv3 runs whose summaries are committed under profiles/ (run from the
@@ -76,15 +75,24 @@ PROFILE_RUNS = {
     "stats": "rocprofv3 --kernel-trace --stats -d $R/gpurun_out/prof_stats -o stats -- "
              "python3 $R/bench.py --steps 5 --warmup 2 --no-cpu-baseline --no-flavor-compare "
              "--no-kernel-compare",
-    "fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-trace -d $R/gpurun_out/prof_fetch -o fetch -- "
-             "python3 $R/bench.py --steps 1 --warmup 0 --radii 3 --ks 32 --no-cpu-baseline "
-             "--no-flavor-compare --no-kernel-compare --copy-calibration-mib 1024",
-    "write": "rocprofv3 --pmc WRITE_SIZE --kernel-trace -d $R/gpurun_out/prof_write -o write -- "
-             "python3 $R/bench.py --steps 1 --warmup 0 --radii 3 --ks 32 --no-cpu-baseline "
-             "--no-flavor-compare --no-kernel-compare --copy-calibration-mib 1024",
 }
-FILL_KERNEL = "k_radius<true"  # the single-tile fill (dense flavor)
+# one step under each counter set (rocprofv3 collects each set in a run of
+# its own); the 1 GiB copy calibrates FETCH_SIZE / WRITE_SIZE
+PMC_SETS = {
+    "fetch": "FETCH_SIZE",
+    "write": "WRITE_SIZE",
+    "insts": ("SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR "
+              "SQ_WAVES SQ_WAVE_CYCLES SQ_WAIT_ANY"),
+    "busy": ("SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_SCA "
+             "SQ_BUSY_CYCLES GRBM_GUI_ACTIVE"),
+}
+for _k, _c in PMC_SETS.items():
+    PROFILE_RUNS[_k] = (f"rocprofv3 --pmc {_c} --kernel-trace -d $R/gpurun_out/prof_{_k} -o {_k} -- "
+                        "python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline "
+                        "--no-flavor-compare --no-kernel-compare --copy-calibration-mib 1024")
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
+N_CU = 256
+N_XCD = 8  # GRBM_GUI_ACTIVE is summed over the XCDs
 
 
 def _db(d):
@@ -103,11 +111,29 @@ def _dispatches(con):
     return [(n, (e - b) / 1e6) for n, b, e in con.execute(q)]
 
 
-def _counter(con, counter):
-    """{dispatch_id: (kernel name, summed counter value)} for one counter."""
-    q = ("select dispatch_id, kernel_name, sum(value) from counters_collection "
-         "where counter_name = ? group by dispatch_id")
-    return {d: (n, v) for d, n, v in con.execute(q, (counter,))}
+def _counters(con):
+    """[(kernel name, {counter: value summed over instances})] in dispatch order."""
+    q = ("select dispatch_id, kernel_name, counter_name, sum(value) from counters_collection "
+         "group by dispatch_id, counter_name order by dispatch_id")
+    out = {}
+    for d, n, c, v in con.execute(q):
+        out.setdefault(d, (n, {}))[1][c] = v
+    return [out[d] for d in sorted(out)]
+
+
+def _hot_kernels(seq, radii, ks):
+    """Label the search launches of one bench step, in their order: the count
+    and fill of each radius, then k-NN per k.  seq: [(name, payload)]."""
+    counts = [x for x in seq if "k_radius" in x[0] and "<false" in x[0]]
+    fills = [x for x in seq if "k_radius" in x[0] and "<true" in x[0]]
+    knns = [x for x in seq if "k_knn<" in x[0]]
+    lab = []
+    for i, r in enumerate(radii):
+        lab.append((f"count r={r:g}", counts[i]))
+        lab.append((f"fill r={r:g}", fills[i]))
+    for i, k in enumerate(ks):
+        lab.append((f"knn k={k}", knns[i]))
+    return lab
 
 
 def agg_profile_summary(stats_dir):
@@ -136,11 +162,13 @@ def agg_profile_summary(stats_dir):
     print(json.dumps({"kernels": len(agg)}))
 
 
-def profile_summary(stats_dir, fetch_dir, write_dir, radii=(0.5, 1.0, 2.0, 3.0), n=10_000_000):
-    """Write the committed rocprofv3 summaries: per-kernel times of the
-    default bench step, and HBM traffic of the radius fill at r = 3 m from
-    FETCH_SIZE / WRITE_SIZE scaled by what the counters read for a 1 GiB
-    device copy."""
+def profile_summary(stats_dir, pmc_root, radii=(0.5, 1.0, 2.0, 3.0), ks=(8, 16, 32),
+                    n=10_000_000):
+    """Write the committed rocprofv3 summaries of the default step (10 M-point
+    ALS tile): per-kernel times; per search launch the instruction mix,
+    LDS bank conflicts, waits and HBM bytes per query; and the HBM traffic of
+    the r = 3 m fill (FETCH_SIZE / WRITE_SIZE scaled by what the counters read
+    for a 1 GiB device copy).  pmc_root holds prof_<set> for every PMC set."""
     out_dir = os.path.join(ROOT, "profiles")
     os.makedirs(out_dir, exist_ok=True)
     # ---- kernel times
@@ -151,69 +179,96 @@ def profile_summary(stats_dir, fetch_dir, write_dir, radii=(0.5, 1.0, 2.0, 3.0),
         a[0] += 1
         a[1] += ms
     total = sum(v[1] for v in agg.values())
-    fills = [ms for name, ms in disp if FILL_KERNEL in name]
-    per_r = {r: fills[i::len(radii)] for i, r in enumerate(radii)}
+    steps = 7  # 2 warm-up + 5 timed
+    lab = {}
+    # the labelled launches of every step, averaged over the steps
+    counts = [(nm, ms) for nm, ms in disp if "k_radius" in nm and "<false" in nm]
+    fills = [(nm, ms) for nm, ms in disp if "k_radius" in nm and "<true" in nm]
+    knns = [(nm, ms) for nm, ms in disp if "k_knn<" in nm]
+    for i, r in enumerate(radii):
+        c = counts[i::len(radii)]
+        f = fills[i::len(radii)]
+        lab[f"count r={r:g}"] = (c[0][0], sum(m for _, m in c) / len(c))
+        lab[f"fill r={r:g}"] = (f[0][0], sum(m for _, m in f) / len(f))
+    for i, k in enumerate(ks):
+        kk = knns[i::len(ks)]
+        lab[f"knn k={k}"] = (kk[0][0], sum(m for _, m in kk) / len(kk))
     lines = ["# Kernel times, default bench step (10 M-point ALS tile)", "",
              "Command (from the repository root R, after `cd /tmp && export TMPDIR=/tmp`):", "",
              "    " + PROFILE_RUNS["stats"], "",
-             "7 steps profiled (2 warm-up + 5 timed).  Per kernel: dispatches, total and "
+             f"{steps} steps profiled (2 warm-up + 5 timed).  Per kernel: dispatches, total and "
              "average duration.", "",
              "| kernel | calls | total ms | avg ms | % |", "|---|---:|---:|---:|---:|"]
     for name, (c, ms) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:25]:
         lines.append(f"| `{name[:90]}` | {c} | {ms:.3f} | {ms / c:.4f} | {100 * ms / total:.1f} |")
-    lines += ["", "Radius fill (`%s`) by radius, average ms per launch:" % FILL_KERNEL, ""]
-    for r in radii:
-        v = per_r[r]
-        if v:
-            lines.append(f"- r = {r} m: {sum(v) / len(v):.3f} ms over {len(v)} launches")
+    lines += ["", "Search launches of a step, average ms per launch:", "",
+              "| launch | kernel | avg ms |", "|---|---|---:|"]
+    for key, (nm, ms) in lab.items():
+        lines.append(f"| {key} | `{nm[:70]}` | {ms:.3f} |")
     with open(os.path.join(out_dir, "kernels_als10m.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
-    # ---- traffic of the fill at r = 3 m
-    fetch = _counter(_db(fetch_dir), "FETCH_SIZE")
-    write = _counter(_db(write_dir), "WRITE_SIZE")
+    # ---- counters of one step
+    pmc = {k: _counters(_db(os.path.join(pmc_root, f"prof_{k}"))) for k in PMC_SETS}
 
-    def pick(cnt, key):
-        return [v for _, (name, v) in sorted(cnt.items()) if key in name]
+    def copy_kib(seq, counter):
+        return max(c.get(counter, 0.0) for nm, c in seq if COPY_KERNEL in nm)
 
     gib = float(1 << 30)
-    # the calibration copy is the largest copy dispatch of the run
-    cf = sorted(pick(fetch, COPY_KERNEL))
-    cw = sorted(pick(write, COPY_KERNEL))
-    ff = pick(fetch, FILL_KERNEL)
-    fw = pick(write, FILL_KERNEL)
-    if not (cf and cw and ff and fw):
-        raise SystemExit("copy or fill kernel missing from the counter runs")
-    f_fac = gib / (cf[-1] * 1024.0)
-    w_fac = gib / (cw[-1] * 1024.0)
-    fill_read = ff[-1] * 1024.0 * f_fac
-    fill_write = fw[-1] * 1024.0 * w_fac
-    rec = {"kernel": "k_radius<fill>", "workload": "10 M-point ALS tile, r = 3 m, every point a query",
-           "commands": {"fetch": PROFILE_RUNS["fetch"], "write": PROFILE_RUNS["write"]},
-           "copy_calibration": {"bytes": 1 << 30, "fetch_kib": cf[-1], "write_kib": cw[-1],
-                                "fetch_factor": f_fac, "write_factor": w_fac},
-           "fill_counters_kib": {"fetch": ff[-1], "write": fw[-1]},
-           "fill_bytes": {"read": fill_read, "write": fill_write},
-           "source_hash": source_hash(),
-           "per_launch_bytes": {"k_radius<fill>@r=3.0": fill_read + fill_write}}
-    with open(os.path.join(out_dir, "radius_fill_als10m_pmc.json"), "w") as fh:
-        json.dump(rec, fh, indent=1)
-    md = ["# HBM traffic of the radius fill, r = 3 m (10 M-point ALS tile)", "",
-          "Commands (from the repository root R, after `cd /tmp && export TMPDIR=/tmp`):", "",
-          "    " + PROFILE_RUNS["fetch"], "    " + PROFILE_RUNS["write"], "",
-          "Calibration: one 1 GiB device copy (`%s`) reads FETCH_SIZE = %.0f KiB and "
-          "WRITE_SIZE = %.0f KiB, so the factors are %.4f (fetch) and %.4f (write)."
-          % (COPY_KERNEL, cf[-1], cw[-1], f_fac, w_fac), "",
-          "| | counter KiB | scaled bytes |", "|---|---:|---:|",
-          f"| read  | {ff[-1]:.0f} | {fill_read:.4g} |",
-          f"| write | {fw[-1]:.0f} | {fill_write:.4g} |",
-          f"| total | | {fill_read + fill_write:.4g} |", "",
-          "Kernel sources hash: `%s` (hash of the kernel sources with comments and "
-          "whitespace removed; bench.py reports this traffic only while the code "
-          "matches)." % rec["source_hash"]]
-    with open(os.path.join(out_dir, "radius_fill_als10m_pmc.md"), "w") as fh:
+    f_fac = gib / (copy_kib(pmc["fetch"], "FETCH_SIZE") * 1024.0)
+    w_fac = gib / (copy_kib(pmc["write"], "WRITE_SIZE") * 1024.0)
+    hot = {k: dict(_hot_kernels(v, radii, ks)) for k, v in pmc.items()}
+    rows = []
+    rec = {}
+    for key in hot["insts"]:
+        nm, ci = hot["insts"][key]
+        cb = hot["busy"][key][1]
+        rd = hot["fetch"][key][1].get("FETCH_SIZE", 0.0) * 1024.0 * f_fac
+        wr = hot["write"][key][1].get("WRITE_SIZE", 0.0) * 1024.0 * w_fac
+        cyc = cb["GRBM_GUI_ACTIVE"] / N_XCD
+        r = dict(kernel=nm, valu_per_query=ci["SQ_INSTS_VALU"] / n,
+                 salu_per_query=ci["SQ_INSTS_SALU"] / n, lds_per_query=ci["SQ_INSTS_LDS"] / n,
+                 vmem_rd_per_query=ci["SQ_INSTS_VMEM_RD"] / n,
+                 vmem_wr_per_query=ci["SQ_INSTS_VMEM_WR"] / n,
+                 valu_per_cu_cycle=ci["SQ_INSTS_VALU"] / (N_CU * cyc),
+                 salu_per_cu_cycle=ci["SQ_INSTS_SALU"] / (N_CU * cyc),
+                 wait_share=ci["SQ_WAIT_ANY"] / max(ci["SQ_WAVE_CYCLES"], 1.0),
+                 lds_bank_conflict_share=cb["SQ_LDS_BANK_CONFLICT"] / max(cb["SQ_ACTIVE_INST_LDS"], 1.0),
+                 read_bytes=rd, write_bytes=wr, bytes_per_query=(rd + wr) / n, gpu_cycles=cyc)
+        rec[key] = r
+        rows.append(f"| {key} | {r['valu_per_query']:.1f} | {r['salu_per_query']:.1f} | "
+                    f"{r['lds_per_query']:.2f} | {r['valu_per_cu_cycle']:.2f} | "
+                    f"{r['salu_per_cu_cycle']:.2f} | {100 * r['wait_share']:.0f} % | "
+                    f"{100 * r['lds_bank_conflict_share']:.1f} % | {rd / 1e9:.2f} | {wr / 1e9:.2f} | "
+                    f"{r['bytes_per_query']:.0f} |")
+    cmds = ["    " + PROFILE_RUNS[k] for k in PMC_SETS]
+    md = ["# Counters of the search kernels, one default step (10 M-point ALS tile, every point "
+          "a query, dense, 1 m voxels)", "",
+          "Commands (from the repository root R, after `cd /tmp && export TMPDIR=/tmp`), one "
+          "counter set per run:", ""] + cmds + [
+          "", "Summary: `python3 bench.py --profile-summary <stats dir> <dir holding prof_<set>>`.",
+          "",
+          "Per launch: wave instructions per query (VALU, SALU, LDS), VALU and SALU wave "
+          "instructions per CU per GPU cycle (GRBM_GUI_ACTIVE per XCD), the share of wave "
+          "cycles spent waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES), LDS bank-conflict cycles per "
+          "active LDS cycle, HBM bytes read and written (FETCH_SIZE x %.4f, WRITE_SIZE x %.4f, "
+          "the factors that make a 1 GiB device copy read and write 1 GiB) and bytes per query."
+          % (f_fac, w_fac), "",
+          "| launch | VALU/q | SALU/q | LDS/q | VALU/CU/cyc | SALU/CU/cyc | waiting | LDS "
+          "conflicts | read GB | written GB | B/q |",
+          "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"] + rows + [
+          "", "Kernel sources hash: `%s` (bench.py reports the r = 3 m fill's traffic only "
+          "while the code matches)." % source_hash()]
+    with open(os.path.join(out_dir, "counters_als10m.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
-    print(json.dumps({"kernels": len(agg), "fill_r3_ms": per_r[radii[-1]],
-                      "fill_traffic": rec["per_launch_bytes"]}), flush=True)
+    fill3 = rec[f"fill r={radii[-1]:g}"]
+    js = {"workload": "10 M-point ALS tile, every point a query, dense, 1 m voxels",
+          "commands": {k: PROFILE_RUNS[k] for k in PMC_SETS},
+          "calibration": {"fetch_factor": f_fac, "write_factor": w_fac},
+          "launches": rec, "source_hash": source_hash(),
+          "per_launch_bytes": {f"fill@r={radii[-1]}": fill3["read_bytes"] + fill3["write_bytes"]}}
+    with open(os.path.join(out_dir, "radius_fill_als10m_pmc.json"), "w") as fh:
+        json.dump(js, fh, indent=1)
+    print(json.dumps({"kernels": len(agg), "fill_traffic": js["per_launch_bytes"]}), flush=True)
 
 
 def cpu_baseline(xyz, radii, ks, cell, sample, nthreads):
@@ -566,7 +621,7 @@ def main():
     ap.add_argument("--batch-r", type=float, default=1.0)
     ap.add_argument("--batch-k", type=int, default=16)
     ap.add_argument("--tune-cache", default=None)
-    ap.add_argument("--profile-summary", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"),
+    ap.add_argument("--profile-summary", nargs=2, metavar=("STATS_DIR", "PMC_ROOT"),
                     help="write the profiles/ summaries from rocprofv3 output directories")
     ap.add_argument("--agg-profile-summary", metavar="STATS_DIR",
                     help="write the aggregation workload's profiles/ summary")
@@ -682,16 +737,24 @@ def main():
     # roofline of the dominant kernel: the radius fill at the largest radius
     # (it writes the CSR lists).  Algorithmic bytes per launch: query records
     # 16 B x Q + row offsets 8 B x Q + every stored point at least once 16 B x N
-    # + neighbour indices 4 B x T.
+    # + neighbour indices 4 B x T.  Beside it, the whole search at that radius
+    # (count + offsets + fill) against the method's own minimum: the FP32
+    # cloud 12 B x N, the centres 12 B x Q, the offsets 8 B x (Q + 1) and the
+    # indices 4 B x T.
     rdom = max(radii)
     T = totals[rdom]
     alg_bytes = 16 * n + 8 * n + 16 * n + 4 * T
     fill_s = phase[f"fill{rdom}"] / 1e3
     achieved = alg_bytes / fill_s / 1e9
-    roof = {"kernel": "k_radius<fill>", "radius_m": rdom, "bound": "hbm", "achieved": achieved,
+    search_bytes = 12 * n + 12 * n + 8 * (n + 1) + 4 * T
+    search_s = (phase[f"count{rdom}"] + phase[f"fill{rdom}"]) / 1e3
+    roof = {"kernel": "radius fill", "radius_m": rdom, "bound": "hbm", "achieved": achieved,
             "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-            "traffic": counter_traffic("k_radius<fill>", rdom),
-            "algorithmic_bytes": alg_bytes, "launch_ms": phase[f"fill{rdom}"]}
+            "traffic": counter_traffic(rdom),
+            "algorithmic_bytes": alg_bytes, "launch_ms": phase[f"fill{rdom}"],
+            "search": {"what": "count + offsets + fill", "algorithmic_bytes": search_bytes,
+                       "ms": search_s * 1e3, "achieved": search_bytes / search_s / 1e9,
+                       "frac": search_bytes / search_s / 1e9 / PEAK_HBM_GBS}}
 
     # the three voxel maps on the same step, one warm and one measured step
     # each, after the timed steps (config 1 compares the flavors)
