@@ -175,16 +175,24 @@ Box kernel_box(const OIndex& ix, const double c[3], double r, int kernel = kSphe
   return b;
 }
 
-void query_coords(const OIndex& ix, const int32_t* pidx, const double* qxyz, int64_t q,
+// The centre of query q; false when the query names no point of the cloud
+// (an index outside [0, n)) or no place (a non-finite coordinate): such a
+// query has no neighbours.
+bool query_coords(const OIndex& ix, const int32_t* pidx, const double* qxyz, int64_t q,
                   float out[3]) {
   if (pidx) {
     int32_t p = pidx[q];
+    if (p < 0 || (int64_t)p >= ix.n) return false;
     for (int a = 0; a < 3; ++a) out[a] = ix.x32[a][p];
   } else if (qxyz) {
-    for (int a = 0; a < 3; ++a) out[a] = (float)(qxyz[q * 3 + a] - ix.origin[a]);
+    for (int a = 0; a < 3; ++a) {
+      if (!std::isfinite(qxyz[q * 3 + a])) return false;
+      out[a] = (float)(qxyz[q * 3 + a] - ix.origin[a]);
+    }
   } else {
     for (int a = 0; a < 3; ++a) out[a] = ix.x32[a][q];
   }
+  return true;
 }
 
 // is_inside for each kernel, in FP32 like the distance: differences
@@ -527,9 +535,9 @@ void* orc_kernel_search(const void* h, const int32_t* pidx, const double* qxyz, 
     std::vector<int32_t>& out = part[t];
     for (int64_t q = a; q < b; ++q) {
       float c[3];
-      query_coords(*ix, pidx, qxyz, q, c);
       size_t before = out.size();
-      radius_one(*ix, c, r, out, visited ? visited + q : nullptr, kernel);
+      if (query_coords(*ix, pidx, qxyz, q, c))
+        radius_one(*ix, c, r, out, visited ? visited + q : nullptr, kernel);
       cnt[q] = (int64_t)(out.size() - before);
     }
   });
@@ -561,8 +569,14 @@ int orc_knn(const void* h, const int32_t* pidx, const double* qxyz, int64_t nq, 
   parallel_for(nq, nthreads, [&](int64_t a, int64_t b) {
     for (int64_t q = a; q < b; ++q) {
       float c[3];
-      query_coords(*ix, pidx, qxyz, q, c);
-      knn_one(*ix, c, k, r_max, idx + q * k, d2 + q * k, visited ? visited + q : nullptr);
+      if (query_coords(*ix, pidx, qxyz, q, c)) {
+        knn_one(*ix, c, k, r_max, idx + q * k, d2 + q * k, visited ? visited + q : nullptr);
+      } else {
+        for (int i = 0; i < k; ++i) {
+          idx[q * k + i] = -1;
+          d2[q * k + i] = INFINITY;
+        }
+      }
     }
   });
   return 0;

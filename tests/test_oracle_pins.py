@@ -437,3 +437,22 @@ def test_agg_gradient_finite_differences():
             num_f[p, c] = (L(x, f + e) - L(x, f - e)) / (2 * h)
     np.testing.assert_allclose(gx, num_x, rtol=1e-6, atol=1e-7)
     np.testing.assert_allclose(gf, num_f, rtol=1e-6, atol=1e-7)
+
+
+def test_invalid_queries_are_empty():
+    """A point index outside the cloud or a non-finite coordinate names no
+    centre: an empty radius row and a k-NN row of (-1, +inf)."""
+    rng = np.random.default_rng(77)
+    xyz = rng.uniform(0, 10, (500, 3))
+    ox = oracle.OracleIndex(xyz, 1.0)
+    q = np.array([3, -1, 500, 10**6, 7], np.int32)
+    off, nbr = ox.radius(2.0, pidx=q)
+    c = np.diff(off)
+    assert c[0] > 0 and c[4] > 0 and (c[1:4] == 0).all()
+    idx, d2 = ox.knn(5, pidx=q)
+    assert (idx[1:4] == -1).all() and np.isinf(d2[1:4]).all() and (idx[[0, 4]] >= 0).all()
+    qa = np.array([[1.0, 2.0, 3.0], [np.nan, 1.0, 1.0], [1.0, np.inf, 0.0]])
+    off, nbr = ox.radius(2.0, qxyz=qa)
+    assert np.diff(off)[0] > 0 and (np.diff(off)[1:] == 0).all()
+    idx, d2 = ox.knn(4, qxyz=qa)
+    assert (idx[1:] == -1).all() and (idx[0] >= 0).all()
