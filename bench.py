@@ -438,15 +438,16 @@ def run_batched(args):
     n = int(toff[-1])
     tuner = Autotuner(cache_path=args.tune_cache)
     t0 = time.perf_counter()
-    cells, flavor = tuner.choose(tiles, r, k)
+    cells, flavor, sched = tuner.choose(tiles, r, k)
     tune_s = time.perf_counter() - t0
-    print(f"[bench] autotune {tune_s:.1f} s ({len(tuner.trials)} trials), flavor {flavor}",
-          file=sys.stderr, flush=True)
+    print(f"[bench] autotune {tune_s:.1f} s ({len(tuner.trials)} trials), flavor {flavor}, "
+          f"radius schedule {sched}", file=sys.stderr, flush=True)
     tuner.save()
     toff_l = toff.tolist()
 
     def batched(keep=False):
         ix = GridIndex(x, cell=cells, flavor=flavor, tile_off=toff_l)
+        ix.set_radius_schedule(sched)
         off, tot = ix.radius_count(r)
         nbr = ix.radius_fill(r, off, tot)
         idx, d2 = ix.knn(k)
@@ -456,6 +457,7 @@ def run_batched(args):
         res = []
         for t in range(T):
             ix = GridIndex(tiles[t], cell=cells[t], flavor=flavor)
+            ix.set_radius_schedule(sched)
             off, tot = ix.radius_count(r)
             nbr = ix.radius_fill(r, off, tot)
             idx, d2 = ix.knn(k)
@@ -521,7 +523,8 @@ def run_batched(args):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{T} ALS tiles, {n} points, sizes log-uniform, densities "
                                f"2-20 pts/m2; radius r={r} m + k-NN k={k} per tile; "
-                               "autotuned voxel edges", "flavor": flavor, "tiles": T,
+                               "autotuned voxel edges", "flavor": flavor,
+                   "radius_schedule": sched, "tiles": T,
                    "n_points": n},
         "batched_ms": t_batch * 1e3,
         "per_tile_ms": t_tile * 1e3,

@@ -139,14 +139,37 @@ chs_status chs_index_info(chs_index index, chs_index_info_t* out /* host */);
  * is a host array of ntiles+1 entries, from 0 to n, strictly increasing).
  * Each tile gets its own bounding box, grid and voxel edges (params[t],
  * host array of ntiles entries, one flavor for all; MIXED is single-tile
- * only).  The tiles' voxel key spaces are concatenated, so keying, sorting
- * and the voxel maps run once for the whole batch.  Searches on a batched
- * index take "every point" queries only (each point queries its own tile);
- * their rows follow the input order and neighbour indices are tile-local
- * (input index minus tile_off[t]). */
+ * only: its slice tables are per z layer of one grid, and a batch's tiles
+ * each have their own z layers).  The tiles' voxel key spaces are
+ * concatenated, so keying, sorting and the voxel maps run once for the
+ * whole batch.  The chs_radius_* / chs_kernel_* / chs_knn searches on a
+ * batched index take "every point" queries (each point queries its own
+ * tile); per-tile query sets go through the *_tiles calls.  Rows follow the
+ * caller's order and neighbour indices are tile-local (input index minus
+ * tile_off[t]). */
 chs_status chs_build_batch(const double* xyz, int64_t n, const int64_t* tile_off /* host */,
                            int32_t ntiles, const chs_build_params* params /* host */,
                            const chs_allocator* alloc, hipStream_t stream, chs_index* out);
+
+/* A batched build that never waits for the stream and reads nothing back
+ * from the device, so that it can be captured in a graph (hipStreamBeginCapture)
+ * and replayed: as chs_build_batch, with each tile's bounding box given by
+ * the caller instead of computed, frames (host, [ntiles][6] FP64: p-_x,
+ * p-_y, p-_z, p+_x, p+_y, p+_z; the corners of Eq. 1-2), and the voxel
+ * tables sized for the worst case (every point its own voxel).  With frames
+ * equal to the tiles' exact minimum and maximum coordinates every array and
+ * search result equals chs_build_batch's; a frame that does not hold its
+ * tile's points gives a valid index whose FP32 frame is fl32(p - frame
+ * minimum), its outlying points in the border voxels.  DENSE or SPARSE only
+ * (MIXED decides its slices from the points: CHS_E_UNSUPPORTED).  The
+ * non-empty voxel count stays on the device until chs_index_info or
+ * chs_index_arrays reads it (they then wait for the stream).  Temporaries
+ * and the index come from `alloc` (under capture: from the capturing
+ * allocator's pool). */
+chs_status chs_build_batch_framed(const double* xyz, int64_t n, const int64_t* tile_off /* host */,
+                                  int32_t ntiles, const chs_build_params* params /* host */,
+                                  const double* frames /* host */, const chs_allocator* alloc,
+                                  hipStream_t stream, chs_index* out);
 
 /* Geometry of one tile of a batched index (n_nonempty is -1). */
 chs_status chs_tile_info(chs_index index, int32_t tile, chs_index_info_t* out /* host */);
@@ -215,8 +238,10 @@ chs_status chs_index_coords(chs_index index, float* out, hipStream_t stream);
 /* Fixed-radius search, count pass (Alg. 1 with a spherical kernel B(c, r),
  * Section 3.4.1): offsets [nq+1] (int64, device) receives the exclusive
  * prefix sum of the per-query neighbour counts |{p : D(c, p) <= fl32(r*r)}|,
- * and *total (host) its last entry.  Synchronises `stream` to read total.
- * r must be finite and >= 0. */
+ * and *total (host) its last entry.  Synchronises `stream` to read total;
+ * with total NULL nothing is read or waited for (the total is offsets[nq] on
+ * the device), so the call can be captured in a graph.  r must be finite
+ * and >= 0. */
 chs_status chs_radius_count(chs_index index, const chs_queries* queries, float r,
                             int64_t* offsets, int64_t* total, hipStream_t stream);
 
@@ -266,6 +291,26 @@ chs_status chs_kernel_fill(chs_index index, const chs_queries* queries, int32_t 
 chs_status chs_kernel_search(chs_index index, const chs_queries* queries, int32_t kernel, float r,
                              const chs_allocator* alloc, int64_t* offsets, int32_t** nbr,
                              int64_t* total, hipStream_t stream);
+
+/* Per-tile query sets on a batched index (the searches of Alg. 1 and Alg. 2
+ * run on each tile's own grid): the queries [q_off[t], q_off[t+1]) belong to
+ * tile t (q_off: host, ntiles+1 entries, from 0 to nq, non-decreasing).
+ * Exactly one of xyz (FP64 absolute; recentred on the tile's p-, Eq. 1) and
+ * point_idx (tile-local: 0 .. n_t - 1; others make empty queries) is given.
+ * Rows follow the caller's order and neighbour indices are tile-local.
+ * Arguments, outputs and errors otherwise as chs_kernel_count /
+ * chs_kernel_fill / chs_knn.  Each call copies its tables from q_off and
+ * waits for the stream once. */
+chs_status chs_kernel_count_tiles(chs_index index, const chs_queries* queries,
+                                  const int64_t* q_off /* host */, int32_t kernel, float r,
+                                  int64_t* offsets, int64_t* total, hipStream_t stream);
+chs_status chs_kernel_fill_tiles(chs_index index, const chs_queries* queries,
+                                 const int64_t* q_off /* host */, int32_t kernel, float r,
+                                 const int64_t* offsets, int32_t* nbr, int64_t total,
+                                 hipStream_t stream);
+chs_status chs_knn_tiles(chs_index index, const chs_queries* queries,
+                         const int64_t* q_off /* host */, int32_t k, float r_max, int32_t* idx,
+                         float* d2, hipStream_t stream);
 
 /* k-nearest-neighbour search (Section 3.4.2): for every query, the min(k, n)
  * points first in the order (D, original index), written to idx [nq,k]

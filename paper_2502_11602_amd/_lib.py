@@ -50,6 +50,9 @@ SIGNATURES = {
     "chs_index_info": (c_int32, [c_void_p, ctypes.POINTER(IndexInfo)]),
     "chs_build_batch": (c_int32, [c_void_p, c_int64, c_void_p, c_int32, c_void_p,
                                   ctypes.POINTER(Allocator), c_void_p, ctypes.POINTER(c_void_p)]),
+    "chs_build_batch_framed": (c_int32, [c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_void_p,
+                                         ctypes.POINTER(Allocator), c_void_p,
+                                         ctypes.POINTER(c_void_p)]),
     "chs_tile_info": (c_int32, [c_void_p, c_int32, ctypes.POINTER(IndexInfo)]),
     "chs_index_set_option": (c_int32, [c_void_p, c_int32, c_int64]),
     "chs_index_arrays": (c_int32, [c_void_p, ctypes.POINTER(IndexArrays)]),
@@ -68,6 +71,12 @@ SIGNATURES = {
     "chs_kernel_search": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_int32, c_float,
                                     ctypes.POINTER(Allocator), c_void_p, ctypes.POINTER(c_void_p),
                                     ctypes.POINTER(c_int64), c_void_p]),
+    "chs_kernel_count_tiles": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_void_p, c_int32,
+                                         c_float, c_void_p, ctypes.POINTER(c_int64), c_void_p]),
+    "chs_kernel_fill_tiles": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_void_p, c_int32,
+                                        c_float, c_void_p, c_void_p, c_int64, c_void_p]),
+    "chs_knn_tiles": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_void_p, c_int32, c_float,
+                                c_void_p, c_void_p, c_void_p]),
     "chs_knn": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_int32, c_float, c_void_p, c_void_p,
                           c_void_p]),
     "chs_knn_noalloc": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_int32, c_float, c_void_p,

@@ -169,11 +169,13 @@ __global__ __launch_bounds__(kThreads) void k_compact_voxels(const K* __restrict
                                                              const int32_t* __restrict__ flag,
                                                              const int32_t* __restrict__ uidx,
                                                              int64_t n, uint64_t* __restrict__ ukeys,
-                                                             int32_t* __restrict__ ustart) {
+                                                             int32_t* __restrict__ ustart,
+                                                             int32_t* __restrict__ m_out) {
   const int64_t pos = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (pos > n) return;
   if (pos == n) {
     ustart[uidx[n]] = (int32_t)n;
+    if (m_out) *m_out = uidx[n];
     return;
   }
   if (flag[pos]) {
@@ -198,11 +200,14 @@ __global__ __launch_bounds__(kThreads) void k_fill_u64(uint64_t* __restrict__ a,
     a[i] = v;
 }
 
+// M: the non-empty voxels, or (m_dev given) their capacity, the count
+// itself being on the device (framed builds)
 __global__ __launch_bounds__(kThreads) void k_voxel_counts(const uint64_t* __restrict__ ukeys,
                                                            const int32_t* __restrict__ ustart,
-                                                           int64_t M, int32_t* __restrict__ cnt) {
+                                                           int64_t M, const int32_t* m_dev,
+                                                           int32_t* __restrict__ cnt) {
   const int64_t u = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (u >= M) return;
+  if (u >= (m_dev ? (int64_t)*m_dev : M)) return;
   cnt[ukeys[u]] = ustart[u + 1] - ustart[u];
 }
 
@@ -222,10 +227,10 @@ __device__ void hash_insert(uint64_t* hk, int32_t* hv, uint64_t mask, uint64_t g
 }
 
 __global__ __launch_bounds__(kThreads) void k_hash_build(const uint64_t* __restrict__ ukeys,
-                                                         int64_t M, uint64_t* hk, int32_t* hv,
-                                                         uint64_t mask) {
+                                                         int64_t M, const int32_t* m_dev,
+                                                         uint64_t* hk, int32_t* hv, uint64_t mask) {
   const int64_t u = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (u >= M) return;
+  if (u >= (m_dev ? (int64_t)*m_dev : M)) return;
   hash_insert(hk, hv, mask, ukeys[u], (int32_t)u);
 }
 
@@ -350,15 +355,24 @@ static chs_status build_sorted(chs_index ix, const double* xyz, int64_t n, const
   k_run_heads<K><<<grid_for(n), kThreads, 0, st>>>(keys.as<K>(), n, flag.as<int32_t>());
   CHS_LAUNCH_CHECK();
   CHS_TRY(exclusive_scan_i32_i32(al, flag.as<int32_t>(), uidx.as<int32_t>(), n));
-  int32_t M = 0;
-  CHS_HIP(hipMemcpyAsync(&M, uidx.as<int32_t>() + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  CHS_HIP(hipStreamSynchronize(st));
-  ix->M = M;
-  CHS_TRY(ix->own(&ix->ukeys, (size_t)M));
-  CHS_TRY(ix->own(&ix->ustart, (size_t)M + 1));
+  if (ix->framed) {
+    // sized for the worst case (every point its own voxel); the count stays
+    // on the device
+    ix->M = -1;
+    CHS_TRY(ix->own(&ix->m_dev, 1));
+    CHS_TRY(ix->own(&ix->ukeys, (size_t)n));
+    CHS_TRY(ix->own(&ix->ustart, (size_t)n + 1));
+  } else {
+    int32_t M = 0;
+    CHS_HIP(hipMemcpyAsync(&M, uidx.as<int32_t>() + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    CHS_HIP(hipStreamSynchronize(st));
+    ix->M = M;
+    CHS_TRY(ix->own(&ix->ukeys, (size_t)M));
+    CHS_TRY(ix->own(&ix->ustart, (size_t)M + 1));
+  }
   k_compact_voxels<K><<<grid_for(n + 1), kThreads, 0, st>>>(keys.as<K>(), flag.as<int32_t>(),
                                                             uidx.as<int32_t>(), n, ix->ukeys,
-                                                            ix->ustart);
+                                                            ix->ustart, ix->m_dev);
   CHS_LAUNCH_CHECK();
   return CHS_OK;
 }
@@ -371,8 +385,9 @@ static chs_status build_dense(chs_index ix) {
   CHS_TRY(cnt.alloc(sizeof(int32_t) * nc));
   k_fill_i32<<<4096, kThreads, 0, st>>>(cnt.as<int32_t>(), nc, 0);
   CHS_LAUNCH_CHECK();
-  k_voxel_counts<<<grid_for(ix->M), kThreads, 0, st>>>(ix->ukeys, ix->ustart, ix->M,
-                                                        cnt.as<int32_t>());
+  const int64_t mcap = ix->M >= 0 ? ix->M : ix->n;
+  k_voxel_counts<<<grid_for(mcap), kThreads, 0, st>>>(ix->ukeys, ix->ustart, mcap, ix->m_dev,
+                                                      cnt.as<int32_t>());
   CHS_LAUNCH_CHECK();
   CHS_TRY(ix->own(&ix->dstart, (size_t)nc + 1));
   CHS_TRY(exclusive_scan_i32_i32(al, cnt.as<int32_t>(), ix->dstart, nc));
@@ -391,9 +406,10 @@ static chs_status alloc_hash(chs_index ix, int64_t nkeys) {
 }
 
 static chs_status build_sparse(chs_index ix) {
-  CHS_TRY(alloc_hash(ix, ix->M));
-  k_hash_build<<<grid_for(ix->M), kThreads, 0, ix->al.stream>>>(ix->ukeys, ix->M, ix->hkeys,
-                                                                 ix->hvals, ix->hcap - 1);
+  const int64_t mcap = ix->M >= 0 ? ix->M : ix->n;
+  CHS_TRY(alloc_hash(ix, mcap));
+  k_hash_build<<<grid_for(mcap), kThreads, 0, ix->al.stream>>>(ix->ukeys, mcap, ix->m_dev,
+                                                               ix->hkeys, ix->hvals, ix->hcap - 1);
   CHS_LAUNCH_CHECK();
   return CHS_OK;
 }
@@ -448,39 +464,54 @@ static chs_status build_mixed(chs_index ix) {
 
 // Build over ntiles tiles (a plain index is one tile).  params[t] gives the
 // voxel edges and dims of tile t; the flavor is that of params[0].
+// frames (host, [ntiles][6] min x,y,z then max x,y,z, or NULL): bounding
+// boxes given by the caller; the build then reads nothing back from the
+// device and never waits for the stream.
 static chs_status build_impl(chs_index ix, const double* xyz, int64_t n, const int64_t* toff,
-                             int ntiles, const chs_build_params* params) {
+                             int ntiles, const chs_build_params* params, const double* frames) {
   const Alloc& al = ix->al;
   hipStream_t st = al.stream;
   ix->ntiles = ntiles;
   ix->tile_off.assign(toff, toff + ntiles + 1);
-  // chunks of at most kBoxChunk points, never straddling two tiles
-  std::vector<Chunk> chunks;
-  std::vector<int32_t> cfirst(ntiles + 1, 0);
-  for (int t = 0; t < ntiles; ++t) {
-    cfirst[t] = (int32_t)chunks.size();
-    for (int64_t b = toff[t]; b < toff[t + 1]; b += kBoxChunk)
-      chunks.push_back(Chunk{b, b + kBoxChunk < toff[t + 1] ? b + kBoxChunk : toff[t + 1]});
-  }
-  cfirst[ntiles] = (int32_t)chunks.size();
-  Buf chunk_d(&al), cfirst_d(&al), part(&al), bb(&al), toff_d(&al), origin_d(&al);
-  CHS_TRY(chunk_d.alloc(sizeof(Chunk) * chunks.size()));
-  CHS_TRY(cfirst_d.alloc(sizeof(int32_t) * (ntiles + 1)));
-  CHS_TRY(part.alloc(sizeof(double) * 7 * chunks.size()));
-  CHS_TRY(bb.alloc(sizeof(double) * 7 * ntiles));
-  CHS_HIP(hipMemcpyAsync(chunk_d.p, chunks.data(), sizeof(Chunk) * chunks.size(),
-                         hipMemcpyHostToDevice, st));
-  CHS_HIP(hipMemcpyAsync(cfirst_d.p, cfirst.data(), sizeof(int32_t) * (ntiles + 1),
-                         hipMemcpyHostToDevice, st));
-  k_bbox_chunks<<<(unsigned)chunks.size(), kThreads, 0, st>>>(xyz, chunk_d.as<Chunk>(),
-                                                               part.as<double>());
-  CHS_LAUNCH_CHECK();
-  k_bbox_tiles<<<(unsigned)ntiles, kThreads, 0, st>>>(part.as<double>(), cfirst_d.as<int32_t>(),
-                                                       bb.as<double>());
-  CHS_LAUNCH_CHECK();
+  ix->framed = frames != nullptr;
+  Buf toff_d(&al), origin_d(&al);
   std::vector<double> h(7 * (size_t)ntiles);
-  CHS_HIP(hipMemcpyAsync(h.data(), bb.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
-  CHS_HIP(hipStreamSynchronize(st));
+  if (frames) {
+    for (int t = 0; t < ntiles; ++t) {
+      for (int a = 0; a < 3; ++a) {
+        h[7 * (size_t)t + a] = frames[6 * (size_t)t + a];
+        h[7 * (size_t)t + 3 + a] = frames[6 * (size_t)t + 3 + a];
+      }
+      h[7 * (size_t)t + 6] = 0.0;
+    }
+  } else {
+    // chunks of at most kBoxChunk points, never straddling two tiles
+    std::vector<Chunk> chunks;
+    std::vector<int32_t> cfirst(ntiles + 1, 0);
+    for (int t = 0; t < ntiles; ++t) {
+      cfirst[t] = (int32_t)chunks.size();
+      for (int64_t b = toff[t]; b < toff[t + 1]; b += kBoxChunk)
+        chunks.push_back(Chunk{b, b + kBoxChunk < toff[t + 1] ? b + kBoxChunk : toff[t + 1]});
+    }
+    cfirst[ntiles] = (int32_t)chunks.size();
+    Buf chunk_d(&al), cfirst_d(&al), part(&al), bb(&al);
+    CHS_TRY(chunk_d.alloc(sizeof(Chunk) * chunks.size()));
+    CHS_TRY(cfirst_d.alloc(sizeof(int32_t) * (ntiles + 1)));
+    CHS_TRY(part.alloc(sizeof(double) * 7 * chunks.size()));
+    CHS_TRY(bb.alloc(sizeof(double) * 7 * ntiles));
+    CHS_HIP(hipMemcpyAsync(chunk_d.p, chunks.data(), sizeof(Chunk) * chunks.size(),
+                           hipMemcpyHostToDevice, st));
+    CHS_HIP(hipMemcpyAsync(cfirst_d.p, cfirst.data(), sizeof(int32_t) * (ntiles + 1),
+                           hipMemcpyHostToDevice, st));
+    k_bbox_chunks<<<(unsigned)chunks.size(), kThreads, 0, st>>>(xyz, chunk_d.as<Chunk>(),
+                                                                 part.as<double>());
+    CHS_LAUNCH_CHECK();
+    k_bbox_tiles<<<(unsigned)ntiles, kThreads, 0, st>>>(part.as<double>(), cfirst_d.as<int32_t>(),
+                                                         bb.as<double>());
+    CHS_LAUNCH_CHECK();
+    CHS_HIP(hipMemcpyAsync(h.data(), bb.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+    CHS_HIP(hipStreamSynchronize(st));
+  }
   ix->tiles.resize(ntiles);
   ix->origin.resize(3 * (size_t)ntiles);
   ix->max32.resize(3 * (size_t)ntiles);
@@ -544,7 +575,9 @@ static chs_status build_impl(chs_index ix, const double* xyz, int64_t n, const i
                          hipMemcpyHostToDevice, st));
   CHS_TRY(toff_d.alloc(sizeof(int64_t) * (ntiles + 1)));
   CHS_TRY(origin_d.alloc(sizeof(double) * 3 * ntiles));
-  CHS_HIP(hipMemcpyAsync(toff_d.p, toff, sizeof(int64_t) * (ntiles + 1), hipMemcpyHostToDevice, st));
+  // (from the index's own copies, which outlive the queued copies)
+  CHS_HIP(hipMemcpyAsync(toff_d.p, ix->tile_off.data(), sizeof(int64_t) * (ntiles + 1),
+                         hipMemcpyHostToDevice, st));
   CHS_HIP(hipMemcpyAsync(origin_d.p, ix->origin.data(), sizeof(double) * 3 * ntiles,
                          hipMemcpyHostToDevice, st));
   const int bits = ceil_log2(ix->total_cells);
@@ -558,15 +591,14 @@ static chs_status build_impl(chs_index ix, const double* xyz, int64_t n, const i
   // the processing order of "every point" queries (searches then plan
   // nothing for them)
   CHS_TRY(plan_every_point(ix, st));
-  // ukeys, ustart, the tile table and the host vectors above are in use
-  // by queued work; wait before they go out of scope
-  CHS_HIP(hipStreamSynchronize(st));
+  // (every host array the queued copies read belongs to the index, and
+  // temporaries are released in stream order: nothing to wait for)
   return CHS_OK;
 }
 
 static chs_status build_common(const double* xyz, int64_t n, const int64_t* toff, int ntiles,
                                const chs_build_params* params, const chs_allocator* alloc,
-                               hipStream_t stream, chs_index* out) {
+                               hipStream_t stream, chs_index* out, const double* frames = nullptr) {
   if (alloc && (!alloc->alloc || !alloc->free)) {
     set_error("allocator callbacks are NULL");
     return CHS_E_INVALID;
@@ -589,7 +621,7 @@ static chs_status build_common(const double* xyz, int64_t n, const int64_t* toff
     delete ix;
     return CHS_E_DEVICE;
   }
-  chs_status s = build_impl(ix, xyz, n, toff, ntiles, params);
+  chs_status s = build_impl(ix, xyz, n, toff, ntiles, params, frames);
   if (s != CHS_OK) {
     std::string msg = last_error();
     chs_free(ix);
@@ -612,11 +644,8 @@ extern "C" chs_status chs_build(const double* xyz, int64_t n, const chs_build_pa
   return build_common(xyz, n, toff, 1, params, alloc, stream, out);
 }
 
-extern "C" chs_status chs_build_batch(const double* xyz, int64_t n, const int64_t* tile_off,
-                                      int32_t ntiles, const chs_build_params* params,
-                                      const chs_allocator* alloc, hipStream_t stream,
-                                      chs_index* out) {
-  clear_error();
+static chs_status check_batch(const double* xyz, int64_t n, const int64_t* tile_off,
+                              int32_t ntiles, const chs_build_params* params, chs_index* out) {
   CHS_TRY(validate(xyz, n, params, out));
   if (!tile_off || ntiles < 1 || ntiles > (1 << 20)) {
     set_error("tile_off is NULL or ntiles = %d outside [1, 2^20]", ntiles);
@@ -641,7 +670,42 @@ extern "C" chs_status chs_build_batch(const double* xyz, int64_t n, const int64_
     set_error("the mixed flavor is not available for batched indexes");
     return CHS_E_UNSUPPORTED;
   }
+  return CHS_OK;
+}
+
+extern "C" chs_status chs_build_batch(const double* xyz, int64_t n, const int64_t* tile_off,
+                                      int32_t ntiles, const chs_build_params* params,
+                                      const chs_allocator* alloc, hipStream_t stream,
+                                      chs_index* out) {
+  clear_error();
+  CHS_TRY(check_batch(xyz, n, tile_off, ntiles, params, out));
   return build_common(xyz, n, tile_off, ntiles, params, alloc, stream, out);
+}
+
+extern "C" chs_status chs_build_batch_framed(const double* xyz, int64_t n,
+                                             const int64_t* tile_off, int32_t ntiles,
+                                             const chs_build_params* params,
+                                             const double* frames, const chs_allocator* alloc,
+                                             hipStream_t stream, chs_index* out) {
+  clear_error();
+  CHS_TRY(check_batch(xyz, n, tile_off, ntiles, params, out));
+  if (!frames) {
+    set_error("frames is NULL");
+    return CHS_E_INVALID;
+  }
+  if (params[0].flavor == CHS_MIXED) {
+    set_error("the mixed flavor sizes its slice tables from the points: not available framed");
+    return CHS_E_UNSUPPORTED;
+  }
+  for (int t = 0; t < ntiles; ++t)
+    for (int a = 0; a < 3; ++a) {
+      const double lo = frames[6 * (size_t)t + a], hi = frames[6 * (size_t)t + 3 + a];
+      if (!std::isfinite(lo) || !std::isfinite(hi) || !(lo <= hi)) {
+        set_error("frame of tile %d: axis %d is not a finite range min <= max", t, a);
+        return CHS_E_INVALID;
+      }
+    }
+  return build_common(xyz, n, tile_off, ntiles, params, alloc, stream, out, frames);
 }
 
 extern "C" void chs_free(chs_index ix) {
@@ -702,12 +766,24 @@ static void fill_info(chs_index ix, int t, chs_index_info_t* out) {
   out->flavor = ix->flavor;
 }
 
+// The non-empty voxel count of a framed index, read from the device on
+// first use (waits for the index's stream).
+static chs_status resolve_m(chs_index ix) {
+  if (ix->M >= 0) return CHS_OK;
+  int32_t m = 0;
+  CHS_HIP(hipMemcpyAsync(&m, ix->m_dev, sizeof(int32_t), hipMemcpyDeviceToHost, ix->al.stream));
+  CHS_HIP(hipStreamSynchronize(ix->al.stream));
+  ix->M = m;
+  return CHS_OK;
+}
+
 extern "C" chs_status chs_index_info(chs_index ix, chs_index_info_t* out) {
   clear_error();
   if (!ix || !out) {
     set_error("index or out is NULL");
     return CHS_E_INVALID;
   }
+  CHS_TRY(resolve_m(ix));
   fill_info(ix, 0, out);
   out->n_points = ix->n;
   out->n_nonempty = ix->M;
@@ -737,6 +813,7 @@ extern "C" chs_status chs_index_arrays(chs_index ix, chs_index_arrays_t* out) {
     set_error("index or out is NULL");
     return CHS_E_INVALID;
   }
+  CHS_TRY(resolve_m(ix));
   out->perm = ix->perm;
   out->inv_perm = ix->inv_perm;
   out->sorted_xyz = ix->sxyz;

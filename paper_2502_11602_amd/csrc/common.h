@@ -146,6 +146,14 @@ struct chs_index_s {
   int32_t* wave_start = nullptr;  //   first query of each wave
   int32_t* tile_qend = nullptr;   //   end of each tile's queries
   int64_t allq_waves = 0;
+  // host data read by copies queued on the stream, kept for the index's
+  // life (so that no build step waits for the stream to free them)
+  std::vector<int32_t> tplan_h;  // per tile: Hilbert bits, z bits, rank, 0
+  std::vector<int32_t> wtile_h, wstart_h, qend_h;
+  // framed builds (bounding boxes given by the caller): nothing is read back
+  // from the device, so the non-empty voxel count stays there until asked
+  bool framed = false;
+  int32_t* m_dev = nullptr;
   std::vector<void*> owned;
 
   int64_t ncells_limit() const { return max_dense; }
@@ -153,7 +161,7 @@ struct chs_index_s {
   chs::Voxels voxels() const {
     chs::Voxels v;
     v.flavor = flavor;
-    v.M = (int32_t)M;
+    v.M = (int32_t)(M >= 0 ? M : n);  // framed: the capacity bounds the ids
     v.npts = n;
     v.dstart = dstart;
     v.hkeys = hkeys;
@@ -406,7 +414,8 @@ struct QueryPlan {
   const int32_t* wave_tile = nullptr;   // batched: tile, first query of each wave
   const int32_t* wave_start = nullptr;
   const int32_t* tile_qend = nullptr;   //   and the end of each tile's queries
-  explicit QueryPlan(const Alloc* al) : q4(al) {}
+  Buf wt, ws, qe;                       // per-tile query sets: those tables
+  explicit QueryPlan(const Alloc* al) : q4(al), wt(al), ws(al), qe(al) {}
 };
 chs_status plan_queries(chs_index ix, const chs_queries* qs, QueryPlan* plan, hipStream_t stream);
 chs_status plan_every_point(chs_index ix, hipStream_t stream);

@@ -4,6 +4,7 @@
 // columns, then k, so that consecutive queries are spatial neighbours; the
 // kernels (radius.hip, knn.hip) take them 64 at a time.
 #include <algorithm>
+#include <cstring>
 #include <cmath>
 
 #include "search_common.h"
@@ -45,7 +46,8 @@ __global__ __launch_bounds__(kThreads) void k_plan_keys(
     const float4* __restrict__ pts, const int32_t* __restrict__ inv_perm,
     const int32_t* __restrict__ perm, int64_t npts, const Grid* __restrict__ tiles,
     TilePlan tp0, const TilePlan* __restrict__ tplan, const int64_t* __restrict__ toff,
-    int ntiles, double ox, double oy, double oz, int lshift, int total_bits, K* __restrict__ keys,
+    const int64_t* __restrict__ qoff, const double* __restrict__ origins, int ntiles, double ox,
+    double oy, double oz, int lshift, int total_bits, K* __restrict__ keys,
     uint32_t* __restrict__ vals, float4* __restrict__ tmp) {
   const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (q >= nq) return;
@@ -57,11 +59,23 @@ __global__ __launch_bounds__(kThreads) void k_plan_keys(
     c = pts[q];
     caller = (uint32_t)perm[q];
     if (ntiles > 1) t = tile_of_point(toff, ntiles, (int64_t)caller);
-  } else if (mode == 1) {  // point indices (single tile)
-    const int32_t p = pidx[q];
-    ok = p >= 0 && (int64_t)p < npts;
+  } else if (mode == 1) {  // point indices (tile-local with per-tile query sets)
+    int64_t p = pidx[q], lo = 0, hi = npts;
+    if (qoff) {
+      t = tile_of_point(qoff, ntiles, q);
+      lo = toff[t];
+      hi = toff[t + 1];
+      p += lo;
+    }
+    ok = p >= lo && p < hi;
     c = ok ? pts[inv_perm[p]] : make_float4(0.f, 0.f, 0.f, 0.f);
-  } else {  // FP64 coordinates (single tile)
+  } else {  // FP64 coordinates (recentred with the query's tile's p-)
+    if (qoff) {
+      t = tile_of_point(qoff, ntiles, q);
+      ox = origins[3 * t];
+      oy = origins[3 * t + 1];
+      oz = origins[3 * t + 2];
+    }
     const double o[3] = {ox, oy, oz};
     float v[3];
     for (int a = 0; a < 3; ++a) {
@@ -80,12 +94,16 @@ __global__ __launch_bounds__(kThreads) void k_plan_keys(
   for (int a = 0; a < 3; ++a)
     if (a < g.dims) cell[a] = voxel_clamped((double)cc[a], g.s[a], g.n[a]);
   K key;
+  // (lshift reaches 64 only for one tile, rank 0)
+  const uint64_t hi_part = lshift >= 64 ? 0ull : ((uint64_t)tp.rank << lshift);
   if (ok) {
     const uint64_t local =
         (hilbert2((uint32_t)cell[0], (uint32_t)cell[1], tp.m) << tp.kbits) | (uint64_t)cell[2];
-    key = (K)(((uint64_t)tp.rank << lshift) | local);
+    key = (K)(hi_part | local);
   } else {
-    key = (K)(total_bits >= 64 ? ~0ull : ((1ull << total_bits) - 1));
+    // last within its tile's range (the tile's waves must hold exactly its
+    // queries)
+    key = (K)(hi_part | (lshift >= 64 ? ~0ull : ((1ull << lshift) - 1)));
   }
   keys[q] = key;
   vals[q] = (uint32_t)q;
@@ -101,10 +119,11 @@ __global__ __launch_bounds__(kThreads) void k_plan_gather(const uint32_t* __rest
   q4[t] = tmp[order[t]];
 }
 
-// Temporaries come from `al` (on stream st).
+// Temporaries come from `al` (on stream st).  q_off (host, ntiles+1): the
+// per-tile query sets of index or coordinate queries on a batched index.
 static chs_status plan_impl(chs_index ix, int mode, const double* xyz, const int32_t* pidx,
                             int64_t nq, const std::vector<int32_t>& rank, float4* q4,
-                            const Alloc& al, hipStream_t st) {
+                            const Alloc& al, hipStream_t st, const int64_t* q_off = nullptr) {
   const int T = ix->ntiles;
   std::vector<TilePlan> tp(T);
   int lshift = 0;
@@ -122,7 +141,8 @@ static chs_status plan_impl(chs_index ix, int mode, const double* xyz, const int
     set_error("query ordering key would need %d bits", bits);
     return CHS_E_CAPACITY;
   }
-  Buf keys(&al), vals(&al), tk(&al), tv(&al), tmp(&al), tp_d(&al), toff_d(&al);
+  Buf keys(&al), vals(&al), tk(&al), tv(&al), tmp(&al), tp_d(&al), toff_d(&al), qoff_d(&al),
+      org_d(&al);
   const bool wide = bits > 32;
   const size_t ks = wide ? 8 : 4;
   CHS_TRY(keys.alloc(ks * nq));
@@ -131,19 +151,31 @@ static chs_status plan_impl(chs_index ix, int mode, const double* xyz, const int
   CHS_TRY(tv.alloc(4 * nq));
   CHS_TRY(tmp.alloc(sizeof(float4) * nq));
   if (T > 1) {
-    // (only the build plans several tiles; it waits for the stream before
-    // these host vectors go out of scope)
+    // (from the index's own copies, which outlive the queued copies)
+    ix->tplan_h.resize(4 * (size_t)T);
+    std::memcpy(ix->tplan_h.data(), tp.data(), sizeof(TilePlan) * T);
     CHS_TRY(tp_d.alloc(sizeof(TilePlan) * T));
     CHS_TRY(toff_d.alloc(sizeof(int64_t) * (T + 1)));
-    CHS_HIP(hipMemcpyAsync(tp_d.p, tp.data(), sizeof(TilePlan) * T, hipMemcpyHostToDevice, st));
+    CHS_HIP(hipMemcpyAsync(tp_d.p, ix->tplan_h.data(), sizeof(TilePlan) * T,
+                           hipMemcpyHostToDevice, st));
     CHS_HIP(hipMemcpyAsync(toff_d.p, ix->tile_off.data(), sizeof(int64_t) * (T + 1),
                            hipMemcpyHostToDevice, st));
+    if (q_off) {
+      // (the calls with per-tile query sets wait for the stream before
+      // returning, so the caller's array outlives this copy)
+      CHS_TRY(qoff_d.alloc(sizeof(int64_t) * (T + 1)));
+      CHS_TRY(org_d.alloc(sizeof(double) * 3 * T));
+      CHS_HIP(hipMemcpyAsync(qoff_d.p, q_off, sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, st));
+      CHS_HIP(hipMemcpyAsync(org_d.p, ix->origin.data(), sizeof(double) * 3 * T,
+                             hipMemcpyHostToDevice, st));
+    }
   }
   const double* o = ix->origin.data();
   if (wide) {
     k_plan_keys<uint64_t><<<grid_for(nq), kThreads, 0, st>>>(
         mode, xyz, pidx, nq, ix->pts, ix->inv_perm, ix->perm, ix->n, ix->tiles_d, tp[0],
-        tp_d.as<TilePlan>(), toff_d.as<int64_t>(), T, o[0], o[1], o[2], lshift, bits,
+        tp_d.as<TilePlan>(), toff_d.as<int64_t>(), qoff_d.as<int64_t>(), org_d.as<double>(), T,
+        o[0], o[1], o[2], lshift, bits,
         keys.as<uint64_t>(), vals.as<uint32_t>(), tmp.as<float4>());
     CHS_LAUNCH_CHECK();
     CHS_TRY(radix_sort_u64(al, keys.as<uint64_t>(), vals.as<uint32_t>(), tk.as<uint64_t>(),
@@ -151,7 +183,8 @@ static chs_status plan_impl(chs_index ix, int mode, const double* xyz, const int
   } else {
     k_plan_keys<uint32_t><<<grid_for(nq), kThreads, 0, st>>>(
         mode, xyz, pidx, nq, ix->pts, ix->inv_perm, ix->perm, ix->n, ix->tiles_d, tp[0],
-        tp_d.as<TilePlan>(), toff_d.as<int64_t>(), T, o[0], o[1], o[2], lshift, bits,
+        tp_d.as<TilePlan>(), toff_d.as<int64_t>(), qoff_d.as<int64_t>(), org_d.as<double>(), T,
+        o[0], o[1], o[2], lshift, bits,
         keys.as<uint32_t>(), vals.as<uint32_t>(), tmp.as<float4>());
     CHS_LAUNCH_CHECK();
     CHS_TRY(radix_sort_u32(al, keys.as<uint32_t>(), vals.as<uint32_t>(), tk.as<uint32_t>(),
@@ -159,7 +192,6 @@ static chs_status plan_impl(chs_index ix, int mode, const double* xyz, const int
   }
   k_plan_gather<<<grid_for(nq), kThreads, 0, st>>>(vals.as<uint32_t>(), tmp.as<float4>(), nq, q4);
   CHS_LAUNCH_CHECK();
-  if (T > 1) CHS_HIP(hipStreamSynchronize(st));  // tp, toff copies read host vectors
   return CHS_OK;
 }
 
@@ -206,7 +238,14 @@ chs_status plan_every_point(chs_index ix, hipStream_t st) {
   al.stream = st;
   CHS_TRY(plan_impl(ix, 0, nullptr, nullptr, ix->n, rank, a, al, st));
   if (T > 1) {
-    std::vector<int32_t> wtile, wstart, qend(T);
+    // the wave tables are the index's own host arrays (the copies below read
+    // them after this returns)
+    std::vector<int32_t>& wtile = ix->wtile_h;
+    std::vector<int32_t>& wstart = ix->wstart_h;
+    std::vector<int32_t>& qend = ix->qend_h;
+    wtile.clear();
+    wstart.clear();
+    qend.assign(T, 0);
     int64_t pos = 0;
     for (int r = 0; r < T; ++r) {
       const int t = (int)order[r];
@@ -224,7 +263,6 @@ chs_status plan_every_point(chs_index ix, hipStream_t st) {
     CHS_HIP(hipMemcpyAsync(ix->wave_tile, wtile.data(), 4 * wtile.size(), hipMemcpyHostToDevice, st));
     CHS_HIP(hipMemcpyAsync(ix->wave_start, wstart.data(), 4 * wstart.size(), hipMemcpyHostToDevice, st));
     CHS_HIP(hipMemcpyAsync(ix->tile_qend, qend.data(), 4 * (size_t)T, hipMemcpyHostToDevice, st));
-    CHS_HIP(hipStreamSynchronize(st));
     ix->allq_waves = (int64_t)wtile.size();
   } else {
     ix->allq_waves = (ix->n + kWave - 1) / kWave;
@@ -255,6 +293,82 @@ chs_status plan_queries(chs_index ix, const chs_queries* qs, QueryPlan* plan, hi
   CHS_TRY(plan_impl(ix, qs->point_idx ? 1 : 2, qs->xyz, qs->point_idx, qs->nq, rank,
                     plan->q4.as<float4>(), *plan->q4.al, st));
   plan->q = plan->q4.as<float4>();
+  return CHS_OK;
+}
+
+// Per-tile query sets on a batched index: queries [q_off[t], q_off[t+1])
+// belong to tile t.  They are planned like "every point" queries (tiles by
+// decreasing query count, waves of at most 64 that never straddle a tile);
+// the wave tables come from the host and the call waits for the stream
+// before its host arrays go.
+static chs_status plan_queries_tiles(chs_index ix, const chs_queries* qs, const int64_t* q_off,
+                                     QueryPlan* plan, hipStream_t st) {
+  const int T = ix->ntiles;
+  plan->nq = qs->nq;
+  plan->nwaves = 0;
+  plan->wave_tile = plan->wave_start = plan->tile_qend = nullptr;
+  if (qs->nq == 0) return CHS_OK;
+  std::vector<int64_t> order(T);
+  for (int t = 0; t < T; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    return q_off[a + 1] - q_off[a] > q_off[b + 1] - q_off[b];
+  });
+  std::vector<int32_t> rank(T);
+  for (int r = 0; r < T; ++r) rank[order[r]] = r;
+  CHS_TRY(plan->q4.alloc(sizeof(float4) * qs->nq));
+  CHS_TRY(plan_impl(ix, qs->point_idx ? 1 : 2, qs->xyz, qs->point_idx, qs->nq, rank,
+                    plan->q4.as<float4>(), *plan->q4.al, st, q_off));
+  plan->q = plan->q4.as<float4>();
+  std::vector<int32_t> wtile, wstart, qend(T);
+  int64_t pos = 0;
+  for (int r = 0; r < T; ++r) {
+    const int t = (int)order[r];
+    const int64_t nt = q_off[t + 1] - q_off[t];
+    for (int64_t b = 0; b < nt; b += kWave) {
+      wtile.push_back(t);
+      wstart.push_back((int32_t)(pos + b));
+    }
+    pos += nt;
+    qend[t] = (int32_t)pos;
+  }
+  plan->nwaves = (int64_t)wtile.size();
+  CHS_TRY(plan->wt.alloc(4 * (wtile.size() + 1)));
+  CHS_TRY(plan->ws.alloc(4 * (wstart.size() + 1)));
+  CHS_TRY(plan->qe.alloc(4 * (size_t)T));
+  if (!wtile.empty()) {
+    CHS_HIP(hipMemcpyAsync(plan->wt.p, wtile.data(), 4 * wtile.size(), hipMemcpyHostToDevice, st));
+    CHS_HIP(hipMemcpyAsync(plan->ws.p, wstart.data(), 4 * wstart.size(), hipMemcpyHostToDevice, st));
+  }
+  CHS_HIP(hipMemcpyAsync(plan->qe.p, qend.data(), 4 * (size_t)T, hipMemcpyHostToDevice, st));
+  CHS_HIP(hipStreamSynchronize(st));
+  plan->wave_tile = plan->wt.as<int32_t>();
+  plan->wave_start = plan->ws.as<int32_t>();
+  plan->tile_qend = plan->qe.as<int32_t>();
+  return CHS_OK;
+}
+
+static chs_status check_tile_queries(chs_index ix, const chs_queries* qs, const int64_t* q_off) {
+  if (!ix || !qs || !q_off) {
+    set_error("index, queries or q_off is NULL");
+    return CHS_E_INVALID;
+  }
+  if (qs->nq != 0 && !!qs->xyz == !!qs->point_idx) {
+    set_error("per-tile query sets: give exactly one of xyz and point_idx");
+    return CHS_E_INVALID;
+  }
+  if (qs->nq < 0 || qs->nq > (int64_t)INT32_MAX) {
+    set_error("queries: nq = %lld outside [0, 2^31 - 1]", (long long)qs->nq);
+    return CHS_E_INVALID;
+  }
+  if (q_off[0] != 0 || q_off[ix->ntiles] != qs->nq) {
+    set_error("q_off must run from 0 to nq over the index's %d tiles", ix->ntiles);
+    return CHS_E_INVALID;
+  }
+  for (int t = 0; t < ix->ntiles; ++t)
+    if (q_off[t + 1] < q_off[t]) {
+      set_error("q_off decreases at tile %d", t);
+      return CHS_E_INVALID;
+    }
   return CHS_OK;
 }
 
@@ -390,8 +504,8 @@ extern "C" chs_status chs_kernel_count(chs_index ix, const chs_queries* qs, int3
   CHS_TRY(check_queries(ix, qs));
   CHS_TRY(check_kernel(kernel));
   CHS_TRY(check_r(r));
-  if (!offsets || !total) {
-    set_error("offsets or total is NULL");
+  if (!offsets) {
+    set_error("offsets is NULL");
     return CHS_E_INVALID;
   }
   Alloc al = ix->al;
@@ -399,6 +513,7 @@ extern "C" chs_status chs_kernel_count(chs_index ix, const chs_queries* qs, int3
   QueryPlan plan(&al);
   CHS_TRY(plan_queries(ix, qs, &plan, st));
   CHS_TRY(radius_count_impl(ix, plan, kernel, r, offsets, st));
+  if (!total) return CHS_OK;  // the total stays on the device, offsets[nq]
   int64_t tot = 0;
   CHS_HIP(hipMemcpyAsync(&tot, offsets + qs->nq, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   CHS_HIP(hipStreamSynchronize(st));
@@ -499,4 +614,81 @@ extern "C" chs_status chs_knn(chs_index ix, const chs_queries* qs, int32_t k, fl
   Alloc al = ix->al;
   al.stream = st;
   return knn_impl(ix, qs, k, r_max, idx, d2, al, st);
+}
+
+// ---- per-tile query sets on a batched index (Alg. 1 and 2 per tile)
+extern "C" chs_status chs_kernel_count_tiles(chs_index ix, const chs_queries* qs,
+                                             const int64_t* q_off, int32_t kernel, float r,
+                                             int64_t* offsets, int64_t* total, hipStream_t st) {
+  clear_error();
+  CHS_TRY(check_tile_queries(ix, qs, q_off));
+  CHS_TRY(check_kernel(kernel));
+  CHS_TRY(check_r(r));
+  if (!offsets || !total) {
+    set_error("offsets or total is NULL");
+    return CHS_E_INVALID;
+  }
+  Alloc al = ix->al;
+  al.stream = st;
+  QueryPlan plan(&al);
+  CHS_TRY(plan_queries_tiles(ix, qs, q_off, &plan, st));
+  CHS_TRY(radius_count_impl(ix, plan, kernel, r, offsets, st));
+  int64_t tot = 0;
+  CHS_HIP(hipMemcpyAsync(&tot, offsets + qs->nq, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  CHS_HIP(hipStreamSynchronize(st));
+  *total = tot;
+  return CHS_OK;
+}
+
+extern "C" chs_status chs_kernel_fill_tiles(chs_index ix, const chs_queries* qs,
+                                            const int64_t* q_off, int32_t kernel, float r,
+                                            const int64_t* offsets, int32_t* nbr, int64_t total,
+                                            hipStream_t st) {
+  clear_error();
+  CHS_TRY(check_tile_queries(ix, qs, q_off));
+  CHS_TRY(check_kernel(kernel));
+  CHS_TRY(check_r(r));
+  if (!offsets || (total > 0 && !nbr) || total < 0) {
+    set_error("offsets or nbr is NULL, or total < 0");
+    return CHS_E_INVALID;
+  }
+  Alloc al = ix->al;
+  al.stream = st;
+  QueryPlan plan(&al);
+  CHS_TRY(plan_queries_tiles(ix, qs, q_off, &plan, st));
+  CHS_TRY(radius_fill_impl(ix, plan, kernel, r, offsets, nbr, total, st));
+  return CHS_OK;
+}
+
+extern "C" chs_status chs_knn_tiles(chs_index ix, const chs_queries* qs, const int64_t* q_off,
+                                    int32_t k, float r_max, int32_t* idx, float* d2,
+                                    hipStream_t st) {
+  clear_error();
+  CHS_TRY(check_tile_queries(ix, qs, q_off));
+  if (k < 1 || k > 64) {
+    set_error("k = %d outside [1, 64]", k);
+    return CHS_E_INVALID;
+  }
+  if (std::isnan(r_max) || r_max < 0.0f) {
+    set_error("r_max must be >= 0 or +inf");
+    return CHS_E_INVALID;
+  }
+  if (qs->nq > 0 && (!idx || !d2)) {
+    set_error("idx or d2 is NULL");
+    return CHS_E_INVALID;
+  }
+  if (qs->nq == 0) return CHS_OK;
+  Alloc al = ix->al;
+  al.stream = st;
+  QueryPlan plan(&al);
+  CHS_TRY(plan_queries_tiles(ix, qs, q_off, &plan, st));
+  const float rmax2 = std::isinf(r_max) ? INFINITY : r_max * r_max;
+  Buf cbuf(&al);
+  int32_t* ctr;
+  unsigned nb;
+  CHS_TRY(launch_dims(ix, plan, st, &cbuf, &ctr, &nb));
+  KnnArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), k, rmax2, idx, d2};
+  launch_knn(ix, nb, st, A);
+  CHS_LAUNCH_CHECK();
+  return CHS_OK;
 }

@@ -100,10 +100,12 @@ class GridIndex:
     With ``tile_off`` (host sequence of ntiles+1 point offsets) the index is
     a batch of independent tiles stored back to back in ``xyz``; ``cell``
     may then be one value per tile.  Searches on a batched index take every
-    point as a query (of its own tile) and return tile-local indices."""
+    point as a query (of its own tile) and return tile-local indices.
+    ``frames`` (per tile: min x, y, z, max x, y, z) makes the batched build
+    read nothing back from the device (it can be captured in a graph)."""
 
     def __init__(self, xyz, cell=1.0, dims=3, flavor="dense", mixed_dense_pct=80,
-                 max_dense_cells=0, stream=None, tile_off=None):
+                 max_dense_cells=0, stream=None, tile_off=None, frames=None):
         if not (isinstance(xyz, torch.Tensor) and xyz.is_cuda and xyz.dtype == torch.float64):
             raise ValueError("xyz must be a float64 CUDA tensor [n,3]")
         if xyz.dim() != 2 or xyz.shape[1] != 3:
@@ -129,10 +131,20 @@ class GridIndex:
                 arr = (BuildParams * T)(*[_params(c, dims, flavor, mixed_dense_pct,
                                                   max_dense_cells) for c in cells])
                 toff_c = (ctypes.c_int64 * (T + 1))(*toff)
-                st = lib().chs_build_batch(xyz.data_ptr(), xyz.shape[0], toff_c, T, arr,
-                                           ctypes.byref(self._alloc.struct), _stream(stream),
-                                           ctypes.byref(h))
-                check(st, "chs_build_batch")
+                if frames is None:
+                    st = lib().chs_build_batch(xyz.data_ptr(), xyz.shape[0], toff_c, T, arr,
+                                               ctypes.byref(self._alloc.struct), _stream(stream),
+                                               ctypes.byref(h))
+                    check(st, "chs_build_batch")
+                else:
+                    fr = [float(v) for f in frames for v in f]
+                    if len(fr) != 6 * T:
+                        raise ValueError("frames: 6 values (min x, y, z, max x, y, z) per tile")
+                    fr_c = (ctypes.c_double * (6 * T))(*fr)
+                    st = lib().chs_build_batch_framed(xyz.data_ptr(), xyz.shape[0], toff_c, T, arr,
+                                                      fr_c, ctypes.byref(self._alloc.struct),
+                                                      _stream(stream), ctypes.byref(h))
+                    check(st, "chs_build_batch_framed")
                 self.ntiles = T
                 self.tile_off = toff
         self._h = h
@@ -221,17 +233,20 @@ class GridIndex:
     # ---- fixed-radius search (Alg. 1)
     KERNELS = {"sphere": 0, "cube": 1, "cylinder": 2}
 
-    def radius_count(self, r, queries=None, stream=None, kernel="sphere"):
+    def radius_count(self, r, queries=None, stream=None, kernel="sphere", sync=True, out=None):
         """Row offsets (int64 [nq+1]) and total of a kernel search; kernel is
-        "sphere", "cube" (half side r) or "cylinder" (radius r, any z)."""
+        "sphere", "cube" (half side r) or "cylinder" (radius r, any z).  With
+        sync=False the total is not read back (None; it is offsets[-1]) and
+        nothing waits for the stream.  ``out``: preallocated offsets."""
         q, nq, keep = _queries(queries, self.n)
-        off = torch.empty(nq + 1, dtype=torch.int64, device=self.device)
+        off = out if out is not None else torch.empty(nq + 1, dtype=torch.int64, device=self.device)
         tot = ctypes.c_int64(0)
         with _on(self.device, stream):
             check(lib().chs_kernel_count(self._h, ctypes.byref(q), self.KERNELS[kernel],
-                                         ctypes.c_float(r), off.data_ptr(), ctypes.byref(tot),
+                                         ctypes.c_float(r), off.data_ptr(),
+                                         ctypes.byref(tot) if sync else None,
                                          _stream(stream)), "chs_kernel_count")
-        return off, tot.value
+        return off, (tot.value if sync else None)
 
     def radius_fill(self, r, offsets, total, queries=None, out=None, stream=None, kernel="sphere"):
         """Fill pass into ``out`` (int32, at least ``total`` entries) or a new
@@ -264,6 +279,45 @@ class GridIndex:
         off, tot = self.radius_count(r, queries, stream, kernel)
         nbr = self.radius_fill(r, off, tot, queries, stream=stream, kernel=kernel)
         return off, nbr
+
+    # ---- per-tile query sets on a batched index
+    def _qoff(self, q_off, nq):
+        qo = [int(v) for v in q_off]
+        if len(qo) != self.ntiles + 1:
+            raise ValueError(f"q_off needs {self.ntiles + 1} entries")
+        return (ctypes.c_int64 * len(qo))(*qo)
+
+    def radius_tiles(self, r, queries, q_off, stream=None, kernel="sphere"):
+        """CSR lists of per-tile query sets: queries[q_off[t]:q_off[t+1]]
+        (tile-local int32 point indices or float64 [.,3] coordinates) search
+        tile t; neighbour indices are tile-local."""
+        q, nq, keep = _queries(queries, self.n)
+        qo = self._qoff(q_off, nq)
+        off = torch.empty(nq + 1, dtype=torch.int64, device=self.device)
+        tot = ctypes.c_int64(0)
+        with _on(self.device, stream):
+            check(lib().chs_kernel_count_tiles(self._h, ctypes.byref(q), qo, self.KERNELS[kernel],
+                                               ctypes.c_float(r), off.data_ptr(), ctypes.byref(tot),
+                                               _stream(stream)), "chs_kernel_count_tiles")
+            nbr = torch.empty(tot.value, dtype=torch.int32, device=self.device)
+            check(lib().chs_kernel_fill_tiles(self._h, ctypes.byref(q), qo, self.KERNELS[kernel],
+                                              ctypes.c_float(r), off.data_ptr(),
+                                              nbr.data_ptr() if tot.value else None, tot.value,
+                                              _stream(stream)), "chs_kernel_fill_tiles")
+        return off, nbr
+
+    def knn_tiles(self, k, queries, q_off, r_max=math.inf, stream=None):
+        """k-NN of per-tile query sets (as radius_tiles)."""
+        q, nq, keep = _queries(queries, self.n)
+        qo = self._qoff(q_off, nq)
+        idx = torch.empty((nq, k), dtype=torch.int32, device=self.device)
+        d2 = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+        with _on(self.device, stream):
+            check(lib().chs_knn_tiles(self._h, ctypes.byref(q), qo, k, ctypes.c_float(r_max),
+                                      idx.data_ptr() if nq else None,
+                                      d2.data_ptr() if nq else None, _stream(stream)),
+                  "chs_knn_tiles")
+        return idx, d2
 
     # ---- k-NN (Section 3.4.2)
     def knn_into(self, k, idx, d2, queries=None, r_max=math.inf, stream=None):

@@ -8,12 +8,14 @@ import torch
 from paper_2502_11602_amd.autotune import Autotuner, compact_sample, tile_stats
 
 
-def test_keys_bucket_size_and_density():
+def test_keys_bucket_size_density_and_aspect():
     k1 = Autotuner.key(100_000, 10.0, 1.0, 16)
     assert k1 == Autotuner.key(110_000, 10.5, 1.0, 16)
     assert k1 != Autotuner.key(400_000, 10.0, 1.0, 16)
     assert k1 != Autotuner.key(100_000, 40.0, 1.0, 16)
     assert k1 != Autotuner.key(100_000, 10.0, 2.0, 16)
+    assert k1 == Autotuner.key(100_000, 10.0, 1.0, 16, aspect=1.2)
+    assert k1 != Autotuner.key(100_000, 10.0, 1.0, 16, aspect=4.0)
 
 
 def test_compact_sample_keeps_density():

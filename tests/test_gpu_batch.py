@@ -165,19 +165,206 @@ def test_batch_rejects_point_queries():
         ix.knn(4, torch.tensor([0, 1], dtype=torch.int32, device=dev))
 
 
-def test_autotuner_picks_a_timed_candidate_and_caches(tmp_path):
-    from paper_2502_11602_amd.autotune import Autotuner
+def test_autotuner_picks_timed_candidates_and_caches(tmp_path):
+    """Every per-tile decision (voxel edge, flavor, query-tile size) is one of
+    the timed trials and the fastest of its stage; a batch's schedule is the
+    one with the smaller summed estimate; a second tuner answers from the
+    cache without timing anything."""
+    from paper_2502_11602_amd.autotune import SCHEDULES, Autotuner
     dev = _dev()
     tiles, _ = _tiles(ntiles=3, seed=11, lo=2000, hi=20000)
     ts = [torch.from_numpy(t).to(dev) for t in tiles]
     tu = Autotuner(cache_path=str(tmp_path / "tune.json"), repeats=1)
-    cells, flavor = tu.choose(ts, 1.0, 16)
-    assert len(cells) == 3 and flavor in ("dense", "sparse")
-    tried = {(t["key"], t["cell"]) for t in tu.trials}
-    for t, c in zip(ts, cells):
-        from paper_2502_11602_amd.autotune import tile_stats
-        n, _, d, _ = tile_stats(t)
-        assert (tu.key(n, d, 1.0, 16), c) in tried
+    for t in ts:
+        ntr = len(tu.trials)
+        cell, flavor, sched, cost = tu.tune(t, 1.0, 16)
+        mine = tu.trials[ntr:]
+        stage1 = [x for x in mine if x["schedule"] == "auto"]
+        stage2 = [x for x in mine if x["schedule"] != "auto"]
+        assert {x["flavor"] for x in stage1} >= {"sparse", "mixed"}
+        assert len({x["cell"] for x in stage1}) >= 5
+        fastest = min(stage1, key=lambda x: x["seconds"])
+        assert (fastest["cell"], fastest["flavor"]) == (cell, flavor)
+        assert {x["schedule"] for x in stage2} == set(SCHEDULES)
+        assert all((x["cell"], x["flavor"]) == (cell, flavor) for x in stage2)
+        assert sched == min(stage2, key=lambda x: x["seconds"])["schedule"]
+        assert SCHEDULES[sched] in (8, 64)
+    cells, flavor, sched = tu.choose(ts, 1.0, 16)
+    assert len(cells) == 3 and flavor in ("dense", "sparse") and sched in SCHEDULES
+    timed = {(x["cell"], x["flavor"]) for x in tu.trials}
+    assert all((c, "sparse") in timed for c in cells)  # every edge was timed
     tu.save()
     again = Autotuner(cache_path=str(tmp_path / "tune.json"), repeats=1)
-    assert again.choose(ts, 1.0, 16)[0] == cells and not again.trials
+    assert again.choose(ts, 1.0, 16) == (cells, flavor, sched) and not again.trials
+
+
+def _frames(tiles):
+    return [list(t.min(0)) + list(t.max(0)) for t in tiles]
+
+
+@pytest.mark.parametrize("flavor", ["dense", "sparse"])
+def test_framed_build_equals_batch_build(flavor):
+    """With every tile's exact bounding box given, the build that reads
+    nothing back from the device gives the same arrays and search results as
+    the batched build (the non-empty voxel count read on demand)."""
+    from paper_2502_11602_amd import GridIndex
+    dev = _dev()
+    tiles, dens = _tiles(ntiles=12, seed=21)
+    cells = [float(np.clip(np.sqrt(8.0 / d), 0.5, 2.0)) for d in dens]
+    x = torch.from_numpy(np.concatenate(tiles)).to(dev)
+    toff = np.concatenate([[0], np.cumsum([len(t) for t in tiles])]).tolist()
+    a = GridIndex(x, cell=cells, flavor=flavor, tile_off=toff)
+    b = GridIndex(x, cell=cells, flavor=flavor, tile_off=toff, frames=_frames(tiles))
+    ia, ib = a.info(), b.info()
+    assert ia["n_nonempty"] == ib["n_nonempty"] and ia["origin"] == ib["origin"]
+    aa, ab = a.arrays(), b.arrays()
+    for key in ("perm", "inv_perm", "sorted_xyz", "points", "cell_keys", "cell_start",
+                "dense_start"):
+        if aa[key] is not None:
+            assert torch.equal(aa[key], ab[key]), key
+    for sched in ("tiles", "groups"):
+        a.set_radius_schedule(sched)
+        b.set_radius_schedule(sched)
+        oa, na = a.radius(1.0)
+        ob, nb = b.radius(1.0)
+        assert torch.equal(oa, ob) and torch.equal(na, nb)
+    ka = a.knn(16)
+    kb = b.knn(16)
+    assert torch.equal(ka[0], kb[0]) and torch.equal(ka[1], kb[1])
+
+
+def test_framed_build_rejects():
+    from paper_2502_11602_amd import ChsError, GridIndex
+    dev = _dev()
+    tiles, _ = _tiles(ntiles=3, seed=22, hi=3000)
+    x = torch.from_numpy(np.concatenate(tiles)).to(dev)
+    toff = np.concatenate([[0], np.cumsum([len(t) for t in tiles])]).tolist()
+    fr = _frames(tiles)
+    with pytest.raises(ChsError, match="UNSUPPORTED"):
+        GridIndex(x, cell=1.0, flavor="mixed", tile_off=toff, frames=fr)
+    bad = [list(f) for f in fr]
+    bad[1][0], bad[1][3] = bad[1][3], bad[1][0]  # min > max
+    with pytest.raises(ChsError, match="INVALID"):
+        GridIndex(x, cell=1.0, tile_off=toff, frames=bad)
+    bad[1][0] = float("nan")
+    with pytest.raises(ChsError, match="INVALID"):
+        GridIndex(x, cell=1.0, tile_off=toff, frames=bad)
+
+
+def test_framed_batch_step_in_two_graphs():
+    """The batched step as two captured graphs: A = framed build + count
+    (+ offsets), nothing read back; then the total is read once and B = fill
+    + k-NN.  Every replay, with eager work in between, equals the eager
+    batched results, which equal the oracle's on sampled tiles."""
+    from paper_2502_11602_amd import GridIndex
+    dev = _dev()
+    tiles, dens = _tiles(ntiles=16, seed=23)
+    cells = [float(np.clip(np.sqrt(8.0 / d), 0.5, 2.0)) for d in dens]
+    x = torch.from_numpy(np.concatenate(tiles)).to(dev)
+    toff = np.concatenate([[0], np.cumsum([len(t) for t in tiles])]).astype(np.int64)
+    fr = _frames(tiles)
+    r, k = 1.0, 16
+    eager = GridIndex(x, cell=cells, flavor="sparse", tile_off=toff.tolist())
+    e_off, e_nbr = eager.radius(r)
+    e_idx, e_d2 = eager.knn(k)
+    off = torch.empty(len(x) + 1, dtype=torch.int64, device=dev)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # warm-up on the capture stream
+        w = GridIndex(x, cell=cells, flavor="sparse", tile_off=toff.tolist(), frames=fr)
+        w.radius_count(r, sync=False, out=off)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    del w
+    ga = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(ga):
+        ix = GridIndex(x, cell=cells, flavor="sparse", tile_off=toff.tolist(), frames=fr)
+        ix.radius_count(r, sync=False, out=off)
+    ga.replay()
+    torch.cuda.synchronize()
+    total = int(off[-1])
+    assert total == int(e_off[-1])
+    nbr = torch.empty(total, dtype=torch.int32, device=dev)
+    idx = torch.empty((len(x), k), dtype=torch.int32, device=dev)
+    d2 = torch.empty((len(x), k), dtype=torch.float32, device=dev)
+    with torch.cuda.stream(s):
+        ix.radius_fill(r, off, total, out=nbr)
+        ix.knn_into(k, idx, d2)
+    torch.cuda.current_stream().wait_stream(s)
+    gb = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gb):
+        ix.radius_fill(r, off, total, out=nbr)
+        ix.knn_into(k, idx, d2)
+    for rep in range(3):
+        off.fill_(-1)
+        nbr.fill_(-7)
+        idx.fill_(-7)
+        torch.cuda.synchronize()
+        _ = e_off.sum()  # eager work between replays
+        ga.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(off, e_off), rep
+        gb.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(nbr, e_nbr), rep
+        assert torch.equal(idx, e_idx) and torch.equal(d2, e_d2), rep
+    offc, nbrc = off.cpu().numpy(), nbr.cpu().numpy()
+    for t in (0, 5, 15):
+        ox = oracle.OracleIndex(tiles[t], cells[t], flavor="sparse")
+        oo, on = ox.radius(r, nthreads=8)
+        a, b = toff[t], toff[t + 1]
+        o2 = offc[a:b + 1] - offc[a]
+        np.testing.assert_array_equal(o2, oo)
+        g = _csr_sorted(o2, nbrc[offc[a]:offc[b]])
+        wv = _csr_sorted(oo, on)
+        np.testing.assert_array_equal(g[1], wv[1])
+        oi, od = ox.knn(k, nthreads=8)
+        np.testing.assert_array_equal(idx[a:b].cpu().numpy(), oi)
+        np.testing.assert_array_equal(d2[a:b].cpu().numpy(), od)
+
+
+@pytest.mark.parametrize("flavor", ["dense", "sparse"])
+def test_tile_query_sets_match_oracle(flavor):
+    """Per-tile query sets on a batched index: tile-local point indices (some
+    out of range) and FP64 coordinates (some outside the tile) per tile, with
+    an empty set for one tile; radius and k-NN rows equal each tile's
+    oracle."""
+    dev = _dev()
+    tiles, dens = _tiles(ntiles=8, seed=24)
+    cells = [1.0] * len(tiles)
+    ix, toff = _batch(tiles, cells, flavor, dev)
+    rng = np.random.default_rng(5)
+    pq, cq = [], []
+    for t, tile in enumerate(tiles):
+        m = 0 if t == 3 else int(rng.integers(50, 400))
+        p = rng.integers(0, len(tile), m).astype(np.int32)
+        if m:
+            p[0] = len(tile)  # out of range: empty row
+        pq.append(p)
+        c = tile[rng.integers(0, len(tile), m)] + rng.normal(0, 0.5, (m, 3))
+        if m:
+            c[0] += 1000.0  # far outside the tile
+        cq.append(c)
+    q_off = np.concatenate([[0], np.cumsum([len(p) for p in pq])]).astype(np.int64)
+    pidx = torch.from_numpy(np.concatenate(pq)).to(dev)
+    cxyz = torch.from_numpy(np.concatenate(cq)).to(dev)
+    for queries, key in ((pidx, "pidx"), (cxyz, "qxyz")):
+        off, nbr = ix.radius_tiles(1.2, queries, q_off)
+        idx, d2 = ix.knn_tiles(12, queries, q_off, r_max=3.0)
+        off, nbr = off.cpu().numpy(), nbr.cpu().numpy()
+        idx, d2 = idx.cpu().numpy(), d2.cpu().numpy()
+        for t, tile in enumerate(tiles):
+            a, b = q_off[t], q_off[t + 1]
+            ox = oracle.OracleIndex(tile, cells[t], flavor=flavor)
+            kw = {key: (pq[t] if key == "pidx" else cq[t])}
+            if b == a:
+                assert off[a] == off[b]
+                continue
+            oo, on = ox.radius(1.2, nthreads=8, **kw)
+            o2 = off[a:b + 1] - off[a]
+            np.testing.assert_array_equal(o2, oo)
+            np.testing.assert_array_equal(_csr_sorted(o2, nbr[off[a]:off[b]])[1],
+                                          _csr_sorted(oo, on)[1])
+            oi, od = ox.knn(12, r_max=3.0, nthreads=8, **kw)
+            np.testing.assert_array_equal(idx[a:b], oi)
+            np.testing.assert_array_equal(d2[a:b], od)
