@@ -430,6 +430,7 @@ def run_batched(args):
     T = len(nt)
     print(f"[bench] generating {T} tiles, {int(nt.sum())} points", file=sys.stderr, flush=True)
     tiles_np = [tile_cloud(t) for t in range(T)]
+    frames = [list(t.min(0)) + list(t.max(0)) for t in tiles_np]
     toff = np.concatenate([[0], np.cumsum([len(t) for t in tiles_np])]).astype(np.int64)
     dev = torch.device("cuda:0")
     x = torch.from_numpy(np.concatenate(tiles_np)).to(dev)
@@ -505,6 +506,47 @@ def run_batched(args):
     torch.cuda.synchronize()
     same_graph = bool(torch.equal(nbr_g, nbr)) and bool(torch.equal(idx_g, idx)) \
         and bool(torch.equal(d2_g, d2))
+    # the whole step as two graphs: A = build from the tiles' frames + count
+    # (nothing read back), one read of the total, B = fill + k-NN
+    off_a = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    nbr_b = torch.empty_like(nbr)
+    idx_b = torch.empty_like(idx)
+    d2_b = torch.empty_like(d2)
+    with torch.cuda.stream(s):
+        wix = GridIndex(x, cell=cells, flavor=flavor, tile_off=toff_l, frames=frames)
+        wix.set_radius_schedule(sched)
+        wix.radius_count(r, sync=False, out=off_a)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    del wix
+    ga = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(ga):
+        gix = GridIndex(x, cell=cells, flavor=flavor, tile_off=toff_l, frames=frames)
+        gix.set_radius_schedule(sched)
+        gix.radius_count(r, sync=False, out=off_a)
+    ga.replay()
+    torch.cuda.synchronize()
+    tot_a = int(off_a[-1])
+    with torch.cuda.stream(s):
+        gix.radius_fill(r, off_a, tot_a, out=nbr_b)
+        gix.knn_into(k, idx_b, d2_b)
+    torch.cuda.current_stream().wait_stream(s)
+    gb = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gb):
+        gix.radius_fill(r, off_a, tot_a, out=nbr_b)
+        gix.knn_into(k, idx_b, d2_b)
+
+    def graphs():
+        ga.replay()
+        t = int(off_a[-1])  # the one read between the graphs
+        assert t == tot_a
+        gb.replay()
+
+    graphs()
+    torch.cuda.synchronize()
+    same_graphs = bool(torch.equal(off_a, off)) and bool(torch.equal(nbr_b, nbr)) \
+        and bool(torch.equal(idx_b, idx)) and bool(torch.equal(d2_b, d2))
+    print(f"[bench] two-graph step == eager: {same_graphs}", file=sys.stderr, flush=True)
     del nbr, idx, d2
     for _ in range(args.warmup):
         batched()
@@ -512,6 +554,7 @@ def run_batched(args):
     t_batch = timed(batched, args.steps)
     t_tile = timed(per_tile, max(1, args.steps // 2))
     t_graph_search = timed(lambda: g.replay(), args.steps)
+    t_graphs = timed(graphs, args.steps)
     out = {
         "metric": "batched uneven tiles: queries per sec, one batched launch sequence vs "
                   "per-tile launches",
@@ -530,8 +573,11 @@ def run_batched(args):
         "per_tile_ms": t_tile * 1e3,
         "speedup_vs_per_tile": t_tile / t_batch,
         "graph_replay_fill_knn_ms": t_graph_search * 1e3,
+        "two_graph_step_ms": t_graphs * 1e3,
+        "two_graph_speedup_vs_per_tile": t_tile / t_graphs,
         "identical_results": same,
         "graph_identical": same_graph,
+        "two_graph_identical": same_graphs,
         "autotune_s": tune_s,
         "cells_m": {"min": min(cells), "max": max(cells)},
     }
