@@ -647,6 +647,96 @@ def run_sweep(args):
     print(json.dumps(out), flush=True)
 
 
+def _split(a, b):
+    """Shares of queries where a visits fewer, more or as many voxels as b."""
+    n = max(len(a), 1)
+    return {"fewer": float((a < b).sum()) / n, "more": float((a > b).sum()) / n,
+            "equal": float((a == b).sum()) / n}
+
+
+def run_knnstats(args):
+    """Density versus monotonic radius growth in k-NN (Section 3.5): on
+    1 M uniform random points (cloudgen.uniform_cube: a 100 m cube, about one
+    point per cubic metre) every point queries its k nearest, dense map, for
+    voxel edges 0.5-4 m and k = 4-32.  The GPU runs the three schedules
+    (rings, density growth, monotonic growth) and counts per query the
+    voxels of its own taboo box under each growth schedule (Alg. 2 run for
+    it alone, the paper's statistic: density growth fewer in 84.5 %, more in
+    3.6 %, equal in 11.9 % of queries, on a cloud whose k and voxel edge it
+    does not state) and of its wave's visited box (what the GPU scans), and
+    times each schedule."""
+    import numpy as np
+    import torch
+
+    import cloudgen
+    from paper_2502_11602_amd import GridIndex
+
+    xyz = cloudgen.uniform_cube()
+    n = xyz.shape[0]
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(xyz).to(dev)
+    E = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    rows = []
+    for cell in (0.5, 1.0, 2.0, 4.0):
+        gi = GridIndex(x, cell=cell, flavor="dense")
+        for k in (4, 8, 16, 32):
+            rec = {"cell_m": cell, "k": k}
+            own, wave, lists = {}, {}, {}
+            for sched in ("rings", "density", "monotonic"):
+                gi.set_knn_schedule(sched)
+                gi.knn(k)
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(max(args.steps, 1)):
+                    a, b = E(), E()
+                    a.record()
+                    idx, d2 = gi.knn(k)
+                    b.record()
+                    torch.cuda.synchronize()
+                    ts.append(a.elapsed_time(b))
+                i2, e2, v = gi.knn_visited(k)
+                v = v.cpu().numpy()
+                own[sched], wave[sched] = v[:, 0], v[:, 1]
+                lists[sched] = bool(torch.equal(idx, i2) and torch.equal(d2, e2))
+                if sched != "rings":
+                    lists[sched] = lists[sched] and bool(torch.equal(idx, ref_i)
+                                                         and torch.equal(d2, ref_d))
+                else:
+                    ref_i, ref_d = idx, d2
+                rec[f"{sched}_ms"] = float(np.median(ts))
+                rec[f"{sched}_mean_wave_voxels"] = float(wave[sched].mean())
+            rec["identical_lists"] = all(lists.values())
+            rec["density_vs_monotonic_own"] = _split(own["density"], own["monotonic"])
+            rec["mean_own_voxels"] = {"density": float(own["density"].mean()),
+                                      "monotonic": float(own["monotonic"].mean())}
+            rec["density_vs_rings_wave"] = _split(wave["density"], wave["rings"])
+            rows.append(rec)
+            print(f"[bench] knnstats s={cell} k={k}: density fewer "
+                  f"{rec['density_vs_monotonic_own']['fewer']:.3f} more "
+                  f"{rec['density_vs_monotonic_own']['more']:.3f}; rings {rec['rings_ms']:.2f} ms,"
+                  f" density {rec['density_ms']:.2f} ms, monotonic {rec['monotonic_ms']:.2f} ms",
+                  file=sys.stderr, flush=True)
+        gi.close()
+    gi = None
+    ref = next(r for r in rows if r["cell_m"] == 1.0 and r["k"] == 16)
+    best = min(ref["rings_ms"], ref["density_ms"], ref["monotonic_ms"])
+    near = min(rows, key=lambda r: abs(r["density_vs_monotonic_own"]["fewer"] - 0.845)
+               + abs(r["density_vs_monotonic_own"]["more"] - 0.036))
+    out = {"metric": "k-NN queries/s, every point a query (uniform random cloud, k = 16)",
+           "value": n / (best / 1e3), "unit": "queries/s", "n_gpus": 1,
+           "steps": max(args.steps, 1), "warmup": 1, "ms_per_step": best,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"{n} uniform random points in a 100 m cube, dense map, "
+                                  "voxel edges 0.5-4 m, k = 4-32 (value: 1 m voxels, k = 16)",
+                      "n_points": n},
+           "paper_density_vs_monotonic": {"fewer": 0.845, "more": 0.036, "equal": 0.119},
+           "closest_row": {"cell_m": near["cell_m"], "k": near["k"],
+                           **near["density_vs_monotonic_own"]},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -664,7 +754,7 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size before the steps "
                          "(a known-size kernel for scaling hardware byte counters)")
-    ap.add_argument("--workload", default="als10m", choices=["als10m", "batched", "sweep", "agg"])
+    ap.add_argument("--workload", default="als10m", choices=["als10m", "batched", "sweep", "agg", "knnstats"])
     ap.add_argument("--agg-cell", type=float, default=0.5)
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--batch-r", type=float, default=1.0)
@@ -697,6 +787,9 @@ def main():
         return
     if args.workload == "agg":
         run_agg(args)
+        return
+    if args.workload == "knnstats":
+        run_knnstats(args)
         return
 
     import numpy as np

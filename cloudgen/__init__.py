@@ -21,3 +21,4 @@ from .als import (  # noqa: F401
     small_als,
 )
 from .tls import tls_cloud, config2  # noqa: F401
+from .uniform import uniform_cube  # noqa: F401

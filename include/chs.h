@@ -186,7 +186,10 @@ chs_status chs_tile_info(chs_index index, int32_t tile, chs_index_info_t* out /*
  * schedule of Alg. 2 (Section 3.4.2): the radius starts at the distance to
  * the nearest wall of the query's voxel (Eq. 11) and grows from the density
  * of the candidates within it (Eq. 12), a query being done once k of them
- * lie within the radius.  Results are identical; only the cost differs. */
+ * lie within the radius.  2 = monotonic growth: as 1 with the radius grown
+ * by the smallest voxel edge at every step, the baseline that Section 3.5
+ * compares density growth with.  Results are identical; only the cost
+ * differs. */
 /* CHS_OPT_FILL_STAGE (default 0): the radius fill stages each query's
  * matches in on-chip memory (LDS) before writing them out, 16, 24 or 32
  * entries per query; 0 picks the size from the mean row length total / nq.
@@ -320,6 +323,27 @@ chs_status chs_knn_tiles(chs_index index, const chs_queries* queries,
  * Does not synchronise. */
 chs_status chs_knn(chs_index index, const chs_queries* queries, int32_t k, float r_max,
                    int32_t* idx, float* d2, hipStream_t stream);
+
+/* chs_knn that also reports how many voxels each query's search visits,
+ * the cost measure by which Section 3.5 compares density growth with
+ * monotonic growth (CHS_OPT_KNN_SCHEDULE picks the schedule).
+ * visited: device, [nq][2] int64, written for every valid query (invalid
+ * queries' entries are left as they are):
+ *   [q][0] the query's own taboo box, Alg. 2 run for it alone: under
+ *          density or monotonic growth the voxels of the padded bounding
+ *          box of B(c, r), clamped to the grid, at the first radius of the
+ *          schedule holding k of its neighbours (or whose box is the whole
+ *          grid; with a finite r_max, at the radius where the search
+ *          stopped); empty voxels count (on a dense map every voxel exists,
+ *          Section 3.5).  Under rings, equal to [q][1];
+ *   [q][1] the visited box of the wave that searched the query together
+ *          with up to 63 nearby ones, when the query's list became final:
+ *          the voxels the GPU actually scanned for it.
+ * A single-tile index without CHS_OPT_PERSISTENT only (CHS_E_UNSUPPORTED
+ * otherwise).  Arguments, results, errors and synchronisation otherwise as
+ * chs_knn. */
+chs_status chs_knn_visited(chs_index index, const chs_queries* queries, int32_t k, float r_max,
+                           int32_t* idx, float* d2, int64_t* visited, hipStream_t stream);
 
 /* chs_knn for callers that cannot allocate device memory (code under graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same

@@ -61,7 +61,7 @@ def lib():
         L.orc_radius_copy.argtypes = [P, P]
         L.orc_radius_free.argtypes = [P]
         L.orc_knn.restype = ctypes.c_int
-        L.orc_knn.argtypes = [P, P, P, i64, ctypes.c_int, f32, ctypes.c_int, P, P, P]
+        L.orc_knn.argtypes = [P, P, P, i64, ctypes.c_int, f32, ctypes.c_int, P, P, P, ctypes.c_int]
         L.orc_agg_fwd.argtypes = [P, P, P, i64, i64, i32, P, i32, f64, P]
         L.orc_agg_bwd.argtypes = [P, P, P, i64, i64, i32, P, i32, f64, P, P, P]
         _lib = L
@@ -166,9 +166,13 @@ class OracleIndex:
             return off, nbr, vis
         return off, nbr
 
-    def knn(self, k, r_max=math.inf, pidx=None, qxyz=None, nthreads=1, visited=False):
+    def knn(self, k, r_max=math.inf, pidx=None, qxyz=None, nthreads=1, visited=False,
+            schedule="density"):
         """Alg. 2 per query; returns idx [nq,k] int32 (-1 padded) and squared
-        distances d2 [nq,k] FP32 (+inf padded), sorted by (d2, index)."""
+        distances d2 [nq,k] FP32 (+inf padded), sorted by (d2, index).
+        schedule: "density" (Alg. 2's growth, Eq. 12) or "monotonic" (the
+        radius grows by the smallest voxel edge per step); with visited=True
+        also the non-empty voxels each query's search visited."""
         pidx, qxyz, nq = self._queries(pidx, qxyz)
         if nq is None:
             nq = self.n
@@ -176,7 +180,7 @@ class OracleIndex:
         d2 = np.zeros((nq, k), np.float32)
         vis = np.zeros(nq, np.int64) if visited else None
         rc = lib().orc_knn(self._h, _p(pidx), _p(qxyz), nq, k, ctypes.c_float(r_max), nthreads,
-                           _p(idx), _p(d2), _p(vis))
+                           _p(idx), _p(d2), _p(vis), {"density": 0, "monotonic": 1}[schedule])
         if rc != 0:
             raise OracleError("orc_knn: invalid argument")
         if visited:

@@ -257,8 +257,12 @@ struct CappedList {
   }
 };
 
+// monotonic: grow the radius by the smallest voxel edge at every step
+// instead of from the density of the candidates found (the baseline the
+// paper compares its density growth with, Section 3.5); the result is the
+// same, only the voxels visited differ.
 void knn_one(const OIndex& ix, const float c32[3], int k, float r_max, int32_t* idx_out,
-             float* d2_out, int64_t* visited) {
+             float* d2_out, int64_t* visited, bool monotonic = false) {
   const double c[3] = {c32[0], c32[1], c32[2]};
   const int nax = ix.dims;
   double s_min = ix.s[0];
@@ -309,7 +313,7 @@ void knn_one(const OIndex& ix, const float c32[3], int k, float r_max, int32_t* 
     for (const Cand& e : cand.v)
       if (e.d <= T) ++np_hat;
     double r_new;
-    if (np_hat > 0) {
+    if (np_hat > 0 && !monotonic) {
       double rho = (double)np_hat / ((4.0 / 3.0) * M_PI * r * r * r);  // Eq. 12
       r_new = std::cbrt((double)k / rho);                               // Alg. 2
       if (!(r_new > r)) r_new = r + s_min;  // density did not make it grow
@@ -563,14 +567,16 @@ void orc_radius_free(void* res) { delete static_cast<RadiusResult*>(res); }
 
 // idx / d2: [nq, k], sorted by (d2, index); padded with (-1, +inf)
 int orc_knn(const void* h, const int32_t* pidx, const double* qxyz, int64_t nq, int k,
-            float r_max, int nthreads, int32_t* idx, float* d2, int64_t* visited) {
+            float r_max, int nthreads, int32_t* idx, float* d2, int64_t* visited,
+            int monotonic) {
   const OIndex* ix = static_cast<const OIndex*>(h);
   if (k < 1 || std::isnan(r_max) || r_max < 0) return 1;
   parallel_for(nq, nthreads, [&](int64_t a, int64_t b) {
     for (int64_t q = a; q < b; ++q) {
       float c[3];
       if (query_coords(*ix, pidx, qxyz, q, c)) {
-        knn_one(*ix, c, k, r_max, idx + q * k, d2 + q * k, visited ? visited + q : nullptr);
+        knn_one(*ix, c, k, r_max, idx + q * k, d2 + q * k, visited ? visited + q : nullptr,
+                monotonic != 0);
       } else {
         for (int i = 0; i < k; ++i) {
           idx[q * k + i] = -1;

@@ -79,6 +79,8 @@ SIGNATURES = {
                                 c_void_p, c_void_p, c_void_p]),
     "chs_knn": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_int32, c_float, c_void_p, c_void_p,
                           c_void_p]),
+    "chs_knn_visited": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_int32, c_float, c_void_p,
+                                  c_void_p, c_void_p, c_void_p]),
     "chs_knn_noalloc": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_int32, c_float, c_void_p,
                                   c_void_p, c_void_p]),
     "chs_gauss_agg_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_int32,

@@ -219,11 +219,49 @@ __device__ __forceinline__ IBox lane_hull(const Grid& g, const float (&qc)[3], d
 // Alg. 2: each lane starts at the distance to the nearest wall of its voxel
 // (Eq. 11), grows its radius from the density of the candidates within it
 // (Eq. 12) or by the smallest voxel edge, and stops once k keys lie within
-// the radius.  The wave visits the hull of its unfinished lanes' kernel
-// boxes.  Both give the exact k nearest.
+// the radius (with A.monotonic the radius always grows by that edge, the
+// baseline Section 3.5 compares density growth with).  The wave visits the
+// hull of its unfinished lanes' kernel boxes.  All give the exact k nearest.
 constexpr int kRings = 0, kDensity = 1;
 
-template <int KC, bool MULTI, int FL, int SCHED>
+__device__ __forceinline__ int64_t box_voxels(const IBox& V, const Grid& g) {
+  int64_t c = 1;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    if (a < g.dims) c *= (int64_t)(V.hi[a] - V.lo[a] + 1);
+  return c;
+}
+
+// One query's own voxels under a growing radius (Alg. 2 run for that query
+// alone): the voxels of the padded box of B(c, r), clamped to the grid,
+// at the first radius of the schedule, from r on, that holds k keys of
+// the (final) sorted list or whose box is the whole grid.
+template <int KC>
+__device__ int64_t own_voxels(const Grid& g, const float (&qc)[3], double r, double smin,
+                              const uint64_t (&best)[KC], int k, bool monotonic) {
+  int64_t grid = 1;
+  for (int a = 0; a < g.dims; ++a) grid *= g.n[a];
+  while (true) {
+    const double pad = fmax(r * (1.0 + kPadRel), kPadAbs);
+    int64_t c = 1;
+    for (int a = 0; a < g.dims; ++a)
+      c *= voxel_clamped((double)qc[a] + pad, g.s[a], g.n[a]) -
+           voxel_clamped((double)qc[a] - pad, g.s[a], g.n[a]) + 1;
+    const uint32_t tb32 = __float_as_uint((float)(r * r));
+    int np = 0;
+#pragma unroll
+    for (int i = 0; i < KC; ++i) np += (uint32_t)(best[i] >> 32) <= tb32 ? 1 : 0;
+    if (np >= k || c == grid) return c;
+    double rn = r + smin;
+    if (np > 0 && !monotonic) {
+      const double rd = cbrt((double)k / ((double)np / ((4.0 / 3.0) * M_PI * r * r * r)));
+      if (rd > r) rn = rd;
+    }
+    r = rn;
+  }
+}
+
+template <int KC, bool MULTI, int FL, int SCHED, bool VIS>
 __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int lane,
                                          uint64_t* seg) {
   const Grid g = MULTI ? A.W.tiles[it.tile] : A.g0;
@@ -242,6 +280,9 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
   for (int i = 0; i < KC; ++i) best[i] = ~0ull;
   uint64_t kthk = ~0ull;
   int nb = 0;
+  // voxels of the wave's visited box when this lane's list became final,
+  // and of the lane's own box (written only when the caller asks for them)
+  int64_t vis = -1, own_vis = -1;
   if (tb.any) {
     const float qc[3] = {q.x, q.y, q.z};
     // density schedule: the lane's radius, starting at the distance from
@@ -345,7 +386,14 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
         if (a >= g.dims) continue;
         if (V.lo[a] > 0 || V.hi[a] < g.n[a] - 1) whole = false;
       }
-      if (whole) break;
+      if (whole) {
+        if (VIS && vis < 0 && active) {
+          vis = box_voxels(V, g);
+          own_vis = SCHED == kDensity ? own_voxels<KC>(g, qc, rL, smin, best, A.k, A.monotonic)
+                                      : vis;
+        }
+        break;
+      }
       if (SCHED == kDensity) {
         // k keys within fl32(rL^2): every unvisited point lies beyond the
         // padded ball of radius rL, so its D exceeds that bound; past the
@@ -354,6 +402,12 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
         const uint32_t tb32 = __float_as_uint(T);
         done = done || (kthk != ~0ull && (uint32_t)(kthk >> 32) <= tb32) ||
                (double)A.rmax2 <= rL * rL;
+        if (VIS && done && vis < 0 && active) {
+          vis = box_voxels(V, g);
+          own_vis = (double)A.rmax2 <= rL * rL
+                        ? own_voxels<KC>(g, qc, rL, smin, best, 0, A.monotonic)
+                        : own_voxels<KC>(g, qc, rL, smin, best, A.k, A.monotonic);
+        }
         if (__ballot(!done) == 0ull) break;
         if (!done) {
           // |P^|: candidates within the radius (Eq. 10); the list is sorted
@@ -361,7 +415,7 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
 #pragma unroll
           for (int i = 0; i < KC; ++i) np += (uint32_t)(best[i] >> 32) <= tb32 ? 1 : 0;
           double rn = rL + smin;  // monotonic growth
-          if (np > 0) {
+          if (np > 0 && !A.monotonic) {
             const double rho = (double)np / ((4.0 / 3.0) * M_PI * rL * rL * rL);  // Eq. 12
             const double rd = cbrt((double)A.k / rho);
             if (rd > rL) rn = rd;
@@ -397,6 +451,7 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
       lb = fmax(lb, 0.0);
       const double lb2 = lb * lb;
       done = !active || (lb2 >= 0x1p-100 && (double)thr < lb2 * (1.0 - kPadRel));
+      if (VIS && done && vis < 0) vis = own_vis = box_voxels(V, g);
       if (__ballot(!done) == 0ull) break;
       tau = wave_max(done ? -INFINITY : (double)thr);
       // next ring: grow the box by one voxel on every side
@@ -407,6 +462,10 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
         B.hi[a] = V.hi[a] < g.n[a] - 1 ? V.hi[a] + 1 : g.n[a] - 1;
       }
     }
+  }
+  if (VIS && active) {
+    A.visited[2 * (int64_t)qid] = own_vis;
+    A.visited[2 * (int64_t)qid + 1] = vis;
   }
   if (in && (int64_t)qid < A.W.nq) {
     int32_t* ro = A.idx + (int64_t)qid * A.k;
@@ -426,49 +485,59 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
 
 // Lists of 32 run at four waves per SIMD, of 16 at six and of 8 at eight:
 // the few registers spilled cost less than the latency hiding gained
-// (measured on the 10 M-point tile).
-template <int KC, bool MULTI, int FL, int SCHED>
+// (measured on the 10 M-point tile).  MODE: 0 = one wave per work item,
+// 1 = persistent waves over a batched or persistent index, 2 = as 0 and
+// reporting the visited voxels (kept out of the other two, whose registers
+// it would cost).
+template <int KC, int MODE, int FL, int SCHED>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KC == 32 ? 4 : (KC == 16 ? 6 : (KC == 8 ? 8 : 1)))))
 void k_knn(KnnArgs A) {
+  constexpr bool MULTI = MODE == 1, VIS = MODE == 2;
   constexpr int kSeg = KnnBuf<KC>::on ? kWave * KnnBuf<KC>::stride : 1;
   __shared__ uint64_t s_buf[kWavesPerBlock * kSeg];
   const int w = threadIdx.x / kWave, lane = lane_id();
   uint64_t* seg = s_buf + w * kSeg + (KnnBuf<KC>::on ? lane * KnnBuf<KC>::stride : 0);
   int64_t own = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
   if (!MULTI) {
-    if (own < A.W.nwaves) knn_item<KC, false, FL, SCHED>(A, item_of(A.W, own), lane, seg);
+    if (own < A.W.nwaves) knn_item<KC, false, FL, SCHED, VIS>(A, item_of(A.W, own), lane, seg);
     return;
   }
   while (true) {
     const int64_t item = next_item(A.W, &own, lane);
     if (item >= A.W.nwaves) break;
-    knn_item<KC, true, FL, SCHED>(A, item_of(A.W, item), lane, seg);
+    knn_item<KC, true, FL, SCHED, false>(A, item_of(A.W, item), lane, seg);
   }
 }
 
 // ---------------------------------------------------------------- launches
+template <int KC, int SCHED, int FL>
+static void launch_knn_f(chs_index ix, unsigned nb, hipStream_t st, const KnnArgs& A) {
+  if (multi(ix))
+    k_knn<KC, 1, FL, SCHED><<<nb, kThreads, 0, st>>>(A);
+  else if (A.visited)
+    k_knn<KC, 2, FL, SCHED><<<nb, kThreads, 0, st>>>(A);
+  else
+    k_knn<KC, 0, FL, SCHED><<<nb, kThreads, 0, st>>>(A);
+}
+
 template <int KC, int SCHED>
 static void launch_knn_s(chs_index ix, unsigned nb, hipStream_t st, const KnnArgs& A) {
-  const bool mt = multi(ix);
   switch (ix->flavor) {
-    case CHS_DENSE:
-      mt ? k_knn<KC, true, CHS_DENSE, SCHED><<<nb, kThreads, 0, st>>>(A)
-         : k_knn<KC, false, CHS_DENSE, SCHED><<<nb, kThreads, 0, st>>>(A);
-      break;
-    case CHS_SPARSE:
-      mt ? k_knn<KC, true, CHS_SPARSE, SCHED><<<nb, kThreads, 0, st>>>(A)
-         : k_knn<KC, false, CHS_SPARSE, SCHED><<<nb, kThreads, 0, st>>>(A);
-      break;
-    default:
-      mt ? k_knn<KC, true, CHS_MIXED, SCHED><<<nb, kThreads, 0, st>>>(A)
-         : k_knn<KC, false, CHS_MIXED, SCHED><<<nb, kThreads, 0, st>>>(A);
+    case CHS_DENSE: launch_knn_f<KC, SCHED, CHS_DENSE>(ix, nb, st, A); break;
+    case CHS_SPARSE: launch_knn_f<KC, SCHED, CHS_SPARSE>(ix, nb, st, A); break;
+    default: launch_knn_f<KC, SCHED, CHS_MIXED>(ix, nb, st, A);
   }
 }
 
 template <int KC>
 static void launch_knn_kc(chs_index ix, unsigned nb, hipStream_t st, const KnnArgs& A) {
-  if (ix->knn_density) launch_knn_s<KC, kDensity>(ix, nb, st, A);
-  else launch_knn_s<KC, kRings>(ix, nb, st, A);
+  if (ix->knn_sched == 0) {
+    launch_knn_s<KC, kRings>(ix, nb, st, A);
+  } else {
+    KnnArgs B = A;
+    B.monotonic = ix->knn_sched == 2;
+    launch_knn_s<KC, kDensity>(ix, nb, st, B);
+  }
 }
 
 void launch_knn(chs_index ix, unsigned nb, hipStream_t st, const KnnArgs& A) {

@@ -465,7 +465,8 @@ static chs_status check_kernel(int32_t kernel) {
 }
 
 chs_status knn_impl(chs_index ix, const chs_queries* qs, int32_t k, float r_max,
-                           int32_t* idx, float* d2, const Alloc& al, hipStream_t st) {
+                           int32_t* idx, float* d2, const Alloc& al, hipStream_t st,
+                           int64_t* visited) {
   CHS_TRY(check_queries(ix, qs));
   if (k < 1 || k > 64) {
     set_error("k = %d outside [1, 64]", k);
@@ -487,7 +488,8 @@ chs_status knn_impl(chs_index ix, const chs_queries* qs, int32_t k, float r_max,
   int32_t* ctr;
   unsigned nb;
   CHS_TRY(launch_dims(ix, plan, st, &cbuf, &ctr, &nb));
-  KnnArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), k, rmax2, idx, d2};
+  KnnArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), k, rmax2, idx, d2,
+            visited};
   launch_knn(ix, nb, st, A);
   CHS_LAUNCH_CHECK();
   return CHS_OK;
@@ -614,6 +616,27 @@ extern "C" chs_status chs_knn(chs_index ix, const chs_queries* qs, int32_t k, fl
   Alloc al = ix->al;
   al.stream = st;
   return knn_impl(ix, qs, k, r_max, idx, d2, al, st);
+}
+
+extern "C" chs_status chs_knn_visited(chs_index ix, const chs_queries* qs, int32_t k,
+                                      float r_max, int32_t* idx, float* d2, int64_t* visited,
+                                      hipStream_t st) {
+  clear_error();
+  if (!ix) {
+    set_error("index is NULL");
+    return CHS_E_INVALID;
+  }
+  if (qs && qs->nq > 0 && !visited) {
+    set_error("visited is NULL");
+    return CHS_E_INVALID;
+  }
+  if (multi(ix)) {
+    set_error("visited voxels are reported on a single-tile index without persistent waves");
+    return CHS_E_UNSUPPORTED;
+  }
+  Alloc al = ix->al;
+  al.stream = st;
+  return knn_impl(ix, qs, k, r_max, idx, d2, al, st, visited);
 }
 
 // ---- per-tile query sets on a batched index (Alg. 1 and 2 per tile)

@@ -204,6 +204,8 @@ struct KnnArgs {
   float rmax2;  // fl32(r_max^2), +inf without a radius cap
   int32_t* __restrict__ idx;
   float* __restrict__ d2;
+  int64_t* __restrict__ visited;  // optional: [nq][2] voxels visited per query
+  int32_t monotonic;  // growth schedule: radius + smallest voxel edge per step
 };
 
 // per-item tile lookups and persistent waves are needed by batched indexes

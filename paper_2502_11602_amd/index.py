@@ -158,9 +158,11 @@ class GridIndex:
         check(lib().chs_index_set_option(self._h, 1, 1 if on else 0), "chs_index_set_option")
 
     def set_knn_schedule(self, schedule="rings"):
-        """k-NN voxel schedule: "rings" (default) or "density" (Alg. 2's
-        density-growth radius); the results are identical."""
-        check(lib().chs_index_set_option(self._h, 4, {"rings": 0, "density": 1}[schedule]),
+        """k-NN voxel schedule: "rings" (default), "density" (Alg. 2's
+        density-growth radius) or "monotonic" (the radius grows by the
+        smallest voxel edge per step); the results are identical."""
+        check(lib().chs_index_set_option(self._h, 4, {"rings": 0, "density": 1,
+                                                      "monotonic": 2}[schedule]),
               "chs_index_set_option")
 
     def tile_info(self, t):
@@ -332,6 +334,23 @@ class GridIndex:
                                 idx.data_ptr() if nq else None, d2.data_ptr() if nq else None,
                                 _stream(stream)), "chs_knn")
         return idx, d2
+
+    def knn_visited(self, k, queries=None, r_max=math.inf, stream=None):
+        """(idx, d2, visited): knn's lists plus, per query, int64 [nq, 2]:
+        [:, 0] the voxels of the query's own taboo box (Alg. 2 run for it
+        alone; rings: as [:, 1]), [:, 1] the voxels of its wave's visited box
+        when its list became final; -1 for invalid queries."""
+        q, nq, keep = _queries(queries, self.n)
+        idx = torch.empty((nq, k), dtype=torch.int32, device=self.device)
+        d2 = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+        vis = torch.full((nq, 2), -1, dtype=torch.int64, device=self.device)
+        with _on(self.device, stream):
+            check(lib().chs_knn_visited(self._h, ctypes.byref(q), k, ctypes.c_float(r_max),
+                                        idx.data_ptr() if nq else None,
+                                        d2.data_ptr() if nq else None,
+                                        vis.data_ptr() if nq else None, _stream(stream)),
+                  "chs_knn_visited")
+        return idx, d2, vis
 
     def knn_noalloc(self, k, idx, d2, queries=None, r_max=math.inf, stream=None):
         """k-NN into preallocated idx / d2 through chs_knn_noalloc: the library

@@ -456,3 +456,68 @@ def test_invalid_queries_are_empty():
     assert np.diff(off)[0] > 0 and (np.diff(off)[1:] == 0).all()
     idx, d2 = ox.knn(4, qxyz=qa)
     assert (idx[1:] == -1).all() and (idx[0] >= 0).all()
+
+
+@pytest.mark.parametrize("name", ["als", "walls"])
+def test_knn_monotonic_schedule_same_lists(name):
+    """Alg. 2 with monotonic radius growth (the baseline of Section 3.5)
+    returns brute force's lists, like density growth, and both count the
+    voxels they visit."""
+    xyz = CLOUDS[name](12)
+    ox = oracle.OracleIndex(xyz, 0.5)
+    q = np.arange(0, len(xyz), 7, dtype=np.int32)
+    i1, d1, v1 = ox.knn(10, pidx=q, visited=True)
+    i2, d2, v2 = ox.knn(10, pidx=q, visited=True, schedule="monotonic")
+    np.testing.assert_array_equal(i1, i2)
+    np.testing.assert_array_equal(d1, d2)
+    pts = ox.point_arrays()["x32"].T
+    bi, bd = brute_knn(pts, pts[q], 10)
+    np.testing.assert_array_equal(i2, bi)
+    np.testing.assert_array_equal(d2, bd)
+    assert (v1 > 0).all() and (v2 > 0).all()
+
+
+def _lattice():
+    """Points at the centres of a 10 x 10 x 10 block of unit voxels, plus
+    two frame points at (0,0,0) and (10,10,10) so that p- = 0 and voxel
+    walls lie on the integers; query: the point at (5.5, 5.5, 5.5)."""
+    g = np.arange(10, dtype=np.float64) + 0.5
+    pts = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    pts = np.vstack([pts, [[0.0, 0.0, 0.0], [10.0, 10.0, 10.0]]])
+    q = int(np.flatnonzero((pts == 5.5).all(1))[0])
+    return pts, q
+
+
+# Worked by hand from Alg. 2 (Section 3.4.2) on the lattice above, voxel
+# edge 1: the start radius is the distance to the nearest wall, 0.5 (Eq. 11);
+# the box of B(c, r), padded by 2^-18 r, spans voxels floor(5.5 - r') ..
+# floor(5.5 + r'), i.e. 3, 5, 7 per axis at r = 0.5, 1.5, 2.5, and 5 at the
+# density radii 1.54 (k = 7) and 2.19 (k = 20).  Lattice neighbours at
+# squared distance <= 0, 2, 4, 6 number 1, 19, 33, 81.  Density growth:
+# r = (k / rho)^(1/3) with rho = 1 / ((4/3) pi 0.5^3) (Eq. 12).  Monotonic
+# growth: r = 0.5, 1.5, 2.5, ...
+@pytest.mark.parametrize("k,dens,mono", [(1, 27, 27), (7, 125, 125), (20, 125, 343),
+                                         (33, 343, 343)])
+def test_knn_visited_voxels_lattice(k, dens, mono):
+    pts, q = _lattice()
+    ox = oracle.OracleIndex(pts, 1.0, flavor="dense")
+    _, _, vd = ox.knn(k, pidx=np.array([q], np.int32), visited=True)
+    _, _, vm = ox.knn(k, pidx=np.array([q], np.int32), visited=True, schedule="monotonic")
+    assert (int(vd[0]), int(vm[0])) == (dens, mono)
+
+
+def test_knn_growth_stats_file_current():
+    """The stored density-vs-monotonic statistic (written by the oracle-only
+    script beside it) is what the oracle gives now, on its row closest to
+    the split Section 3.5 reports (voxel edge 2 m, k = 8)."""
+    import importlib.util
+    import os
+    spec = importlib.util.spec_from_file_location(
+        "mkstats", os.path.join(os.path.dirname(__file__), "golden", "make_knn_growth_stats.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    rows = {(float(c), int(v[0])): tuple(int(x) for x in v[1:])
+            for c, vals in golden("knn_growth_stats.txt").items() for v in vals}
+    got = next(mk.rows(8, cells=[2.0], ks=[8]))
+    assert rows[(2.0, 8)] == tuple(got[2:])
+    assert sum(rows[(2.0, 8)][:3]) == 1_000_000
