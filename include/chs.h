@@ -250,16 +250,36 @@ chs_status chs_radius_count(chs_index index, const chs_queries* queries, float r
 
 /* Fill pass of Alg. 1 (Section 3.4.1; the points inside the kernel are
  * appended to the query's list): writes the original indices of each
- * query's neighbours into nbr[offsets[q] .. offsets[q+1]) (int32, device,
- * `total` entries, as given by chs_radius_count for the same queries and r).
- * The order inside a row is deterministic but unspecified (the neighbour
- * relation is a set).  Every write stays inside nbr[0, total): a row is
- * clipped at total, and a row with offsets[q] < 0 or offsets[q] >
- * offsets[q+1] is not written, so offsets that belong to other queries or
- * another r give wrong rows but never write outside nbr. */
+ * query's neighbours into nbr[offsets[q] - offsets[0] .. offsets[q+1] -
+ * offsets[0]) (int32, device, `total` entries, as given by
+ * chs_radius_count for the same queries and r, where offsets[0] = 0).  A
+ * consecutive range [a, b) of a counted set fills on its own with the
+ * queries and offsets advanced by a (offsets + a, base offsets[a]) and total
+ * = offsets[b] - offsets[a]: rows too many for one buffer are filled range
+ * by range (chs_fill_chunks picks the ranges).  The order inside a row is
+ * deterministic but unspecified (the neighbour relation is a set).  Every
+ * write stays inside nbr[0, total): a row is clipped at total, and a row
+ * that starts before offsets[0] or has offsets[q] > offsets[q+1] is not
+ * written, so offsets that belong to other queries or another r give wrong
+ * rows but never write outside nbr. */
 chs_status chs_radius_fill(chs_index index, const chs_queries* queries, float r,
                            const int64_t* offsets, int32_t* nbr, int64_t total,
                            hipStream_t stream);
+
+/* Splits a counted set of nq queries into consecutive ranges that each
+ * fill within max_entries neighbour entries (a memory budget for the fill's
+ * output), as few as possible: bounds (host) receives q_0 = 0 < q_1 < ... <
+ * q_m = nq and entry_bounds (host) offsets[q_i], so range i is the queries
+ * [q_i, q_{i+1}) with entry_bounds[i+1] - entry_bounds[i] entries.  offsets:
+ * device, [nq+1], from chs_radius_count / chs_kernel_count.  *nchunks
+ * (host) = m.  With cap = 0 only *nchunks is computed (bounds and
+ * entry_bounds may be NULL); otherwise they hold cap entries and cap < m + 1
+ * is CHS_E_CAPACITY (*nchunks set).  A single query with more than
+ * max_entries neighbours is CHS_E_CAPACITY; decreasing offsets are
+ * CHS_E_INVALID.  Copies offsets to the host and synchronises `stream`. */
+chs_status chs_fill_chunks(const int64_t* offsets, int64_t nq, int64_t max_entries,
+                           int64_t* bounds /* host */, int64_t* entry_bounds /* host */,
+                           int64_t cap, int64_t* nchunks /* host */, hipStream_t stream);
 
 /* The whole fixed-radius search of Alg. 1 (Section 3.4.1): count +
  * allocation of the neighbour array through `alloc` (NULL = the index's

@@ -128,10 +128,13 @@ __device__ __forceinline__ void radius_tile_item(const RadiusArgs& A, const Item
   int nb = 0;
   int32_t* my_seg = seg_base + (FILL ? lane * Stage<ST>::stride : 0);
   if (FILL && active) {
-    // rows are clipped to nbr's extent: offsets that do not belong to these
-    // queries and this r write nothing outside [0, total)
-    wpos = A.offsets[qid];
-    wend = A.offsets[qid + 1];
+    // rows start at offsets[q] - offsets[0] (a range of a larger counted
+    // set fills its own buffer) and are clipped to nbr's extent: offsets
+    // that do not belong to these queries and this r write nothing outside
+    // [0, total)
+    const int64_t base = A.offsets[0];
+    wpos = A.offsets[qid] - base;
+    wend = A.offsets[qid + 1] - base;
     if (wend > A.total) wend = A.total;
     if (wpos < 0 || wpos > wend) wpos = wend = 0;
   }
@@ -400,11 +403,12 @@ __device__ __forceinline__ void radius_group_item(const RadiusArgs& A, const Ite
           asm volatile("v_mov_b32 %0, %1" : "=v"(qz[j]) : "s"(qz[j]));
         }
         if (FILL && qa[j]) {
-          // rows are clipped to nbr's extent: offsets that do not belong to
-          // these queries and this r write nothing outside [0, total); a
-          // row holds fewer than 2^31 entries (the counts are int32)
+          // rows start at offsets[q] - offsets[0] and are clipped to nbr's
+          // extent: offsets that do not belong to these queries and this r
+          // write nothing outside [0, total); a row holds fewer than 2^31
+          // entries (the counts are int32)
           const const_i64 co = (const_i64)A.offsets;
-          int64_t rb = co[w], re = co[w + 1];
+          int64_t rb = co[w] - co[0], re = co[w + 1] - co[0];
           if (re > A.total) re = A.total;
           if (rb < 0 || rb > re) rb = re = 0;
           row[j] = (global_i32)A.nbr + rb;

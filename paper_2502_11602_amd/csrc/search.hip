@@ -542,6 +542,55 @@ extern "C" chs_status chs_kernel_fill(chs_index ix, const chs_queries* qs, int32
   return CHS_OK;
 }
 
+extern "C" chs_status chs_fill_chunks(const int64_t* offsets, int64_t nq, int64_t max_entries,
+                                      int64_t* bounds, int64_t* entry_bounds, int64_t cap,
+                                      int64_t* nchunks, hipStream_t st) {
+  clear_error();
+  if (!offsets || !nchunks || nq < 0 || max_entries < 1 || cap < 0 ||
+      (cap > 0 && (!bounds || !entry_bounds))) {
+    set_error("offsets or nchunks is NULL, nq < 0, max_entries < 1, or bounds missing");
+    return CHS_E_INVALID;
+  }
+  std::vector<int64_t> off((size_t)nq + 1);
+  CHS_HIP(hipMemcpyAsync(off.data(), offsets, off.size() * sizeof(int64_t),
+                         hipMemcpyDeviceToHost, st));
+  CHS_HIP(hipStreamSynchronize(st));
+  for (int64_t q = 0; q < nq; ++q)
+    if (off[q + 1] < off[q]) {
+      set_error("offsets decrease at query %lld", (long long)q);
+      return CHS_E_INVALID;
+    }
+  // greedy: each range takes as many further queries as fit, which gives
+  // the fewest ranges
+  std::vector<int64_t> b{0};
+  while (b.back() < nq) {
+    const int64_t q = b.back();
+    const int64_t room = off[(size_t)nq] - off[q];
+    const int64_t lim = max_entries >= room ? off[(size_t)nq] : off[q] + max_entries;
+    const int64_t e =
+        (int64_t)(std::upper_bound(off.begin() + q + 1, off.end(), lim) - off.begin()) - 1;
+    if (e == q) {
+      set_error("query %lld alone has %lld entries > max_entries", (long long)q,
+                (long long)(off[q + 1] - off[q]));
+      return CHS_E_CAPACITY;
+    }
+    b.push_back(e);
+  }
+  const int64_t m = (int64_t)b.size() - 1;
+  *nchunks = m;
+  if (cap == 0) return CHS_OK;
+  if (cap < m + 1) {
+    set_error("%lld ranges need %lld bound entries, cap is %lld", (long long)m,
+              (long long)(m + 1), (long long)cap);
+    return CHS_E_CAPACITY;
+  }
+  for (int64_t i = 0; i <= m; ++i) {
+    bounds[i] = b[(size_t)i];
+    entry_bounds[i] = off[(size_t)b[(size_t)i]];
+  }
+  return CHS_OK;
+}
+
 extern "C" chs_status chs_kernel_search(chs_index ix, const chs_queries* qs, int32_t kernel,
                                         float r, const chs_allocator* alloc, int64_t* offsets,
                                         int32_t** nbr, int64_t* total, hipStream_t st) {

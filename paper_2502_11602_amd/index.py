@@ -274,6 +274,45 @@ class GridIndex:
                                         _stream(stream)), "chs_kernel_fill")
         return nbr
 
+    def fill_chunks(self, offsets, max_entries, stream=None):
+        """Query ranges whose fills each hold at most max_entries entries
+        (chs_fill_chunks): host lists bounds [q_0 = 0, ..., q_m = nq] and
+        entry_bounds [offsets[q_i]]."""
+        nq = offsets.numel() - 1
+        m = ctypes.c_int64(0)
+        with _on(self.device, stream):
+            check(lib().chs_fill_chunks(offsets.data_ptr(), nq, int(max_entries), None, None, 0,
+                                        ctypes.byref(m), _stream(stream)), "chs_fill_chunks")
+            b = (ctypes.c_int64 * (m.value + 1))()
+            e = (ctypes.c_int64 * (m.value + 1))()
+            check(lib().chs_fill_chunks(offsets.data_ptr(), nq, int(max_entries), b, e,
+                                        m.value + 1, ctypes.byref(m), _stream(stream)),
+                  "chs_fill_chunks")
+        return list(b), list(e)
+
+    def radius_chunked(self, r, queries, max_entries, stream=None, kernel="sphere",
+                       offsets=None):
+        """Count all queries (index or coordinate queries), then yield
+        (a, b, nbr) per range of queries [a, b) whose neighbour rows fit
+        max_entries entries: nbr is a view of one reused int32 buffer holding
+        the range's CSR rows (offsets[a:b+1] - offsets[a]); it is overwritten
+        by the next range.  Returns the offsets of all queries when exhausted
+        (StopIteration.value)."""
+        if queries is None:
+            raise ValueError("ranges need explicit queries (point indices or coordinates)")
+        if offsets is None:
+            offsets, _ = self.radius_count(r, queries, stream, kernel)
+        bounds, ebounds = self.fill_chunks(offsets, max_entries, stream)
+        buf = torch.empty(max(1, min(int(max_entries), ebounds[-1])), dtype=torch.int32,
+                          device=self.device)
+        for i in range(len(bounds) - 1):
+            a, b = bounds[i], bounds[i + 1]
+            tot = ebounds[i + 1] - ebounds[i]
+            nbr = self.radius_fill(r, offsets[a:b + 1], tot, queries[a:b], out=buf,
+                                   stream=stream, kernel=kernel)
+            yield a, b, nbr[:tot]
+        return offsets
+
     def radius(self, r, queries=None, stream=None, kernel="sphere"):
         """CSR neighbour lists: (offsets int64 [nq+1], nbr int32 [total]) of
         original point indices inside the kernel around each query (the

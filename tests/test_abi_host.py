@@ -118,3 +118,20 @@ def test_coords_reject_null(L):
 
 def test_set_option_rejects_bad_values(L):
     assert L.chs_index_set_option(None, 5, 16) == 1
+
+
+def test_fill_chunks_reject_invalid(L):
+    # checked on the host before any device access
+    m = ctypes.c_int64(-1)
+    assert L.chs_fill_chunks(None, 4, 10, None, None, 0, ctypes.byref(m), None) == 1
+    assert L.chs_fill_chunks(FAKE, 4, 0, None, None, 0, ctypes.byref(m), None) == 1
+    assert L.chs_fill_chunks(FAKE, -1, 10, None, None, 0, ctypes.byref(m), None) == 1
+    assert L.chs_fill_chunks(FAKE, 4, 10, None, None, 3, ctypes.byref(m), None) == 1
+    assert L.chs_fill_chunks(FAKE, 4, 10, None, None, 0, None, None) == 1
+
+
+def test_knn_visited_rejects_null(L):
+    from paper_2502_11602_amd._lib import Queries
+    q = Queries(None, None, 5)
+    assert L.chs_knn_visited(None, ctypes.byref(q), 8, float("inf"), FAKE, FAKE, FAKE, None) == 1
+    assert b"NULL" in L.chs_last_error()

@@ -222,3 +222,66 @@ def test_coords_are_the_oracle_frame():
     x32 = gi.coords().cpu().numpy()
     o = oracle.OracleIndex(xyz, 1.0).point_arrays()["x32"]
     np.testing.assert_array_equal(x32, o.T)
+
+
+def test_fill_by_ranges():
+    """A counted query set filled range by range (chs_fill_chunks picks the
+    ranges under an entry budget; each range fills with the queries and
+    offsets advanced to its start) gives the rows of one whole fill, for
+    index and coordinate queries and both radius schedules."""
+    from paper_2502_11602_amd import GridIndex
+    dev = _dev()
+    xyz = _cloud()
+    gi = GridIndex(torch.from_numpy(xyz).to(dev), cell=1.0)
+    rng = np.random.default_rng(3)
+    qi = torch.from_numpy(rng.choice(len(xyz), 5000, replace=False).astype(np.int32)).to(dev)
+    qa = torch.from_numpy(rng.uniform(xyz.min(0), xyz.max(0), (4000, 3))).to(dev)
+    for sched in ("tiles", "groups"):
+        gi.set_radius_schedule(sched)
+        for q in (qi, qa):
+            off, nbr = gi.radius(2.0, q)
+            total = int(off[-1])
+            for budget in (total, total // 7 + 1, 1000):
+                bounds, eb = gi.fill_chunks(off, budget)
+                offc = off.cpu().numpy()
+                assert bounds[0] == 0 and bounds[-1] == len(q)
+                assert eb == [int(offc[b]) for b in bounds]
+                sizes = np.diff(eb)
+                assert (sizes <= budget).all()
+                # fewest ranges: no range could take the next query too
+                for i in range(len(bounds) - 2):
+                    assert offc[bounds[i + 1] + 1] - offc[bounds[i]] > budget
+                parts = []
+                for a, b, part in gi.radius_chunked(2.0, q, budget, offsets=off):
+                    rows = np.split(part.cpu().numpy(), offc[a + 1:b] - offc[a])
+                    parts += [np.sort(r) for r in rows]
+                want = np.split(nbr.cpu().numpy(), offc[1:-1])
+                assert len(parts) == len(want)
+                for g, w in zip(parts, want):
+                    np.testing.assert_array_equal(g, np.sort(w))
+
+
+def test_fill_chunks_rejects():
+    from paper_2502_11602_amd import ChsError
+    from paper_2502_11602_amd._lib import lib
+    dev = _dev()
+    off = torch.tensor([0, 5, 9, 30, 31], dtype=torch.int64, device=dev)
+    from paper_2502_11602_amd import GridIndex
+    gi = GridIndex(torch.from_numpy(_cloud(n=2000)).to(dev), cell=1.0)
+    assert gi.fill_chunks(off, 22) == ([0, 2, 4], [0, 9, 31])
+    assert gi.fill_chunks(off, 21) == ([0, 2, 3, 4], [0, 9, 30, 31])
+    assert gi.fill_chunks(off, 1000) == ([0, 4], [0, 31])
+    with pytest.raises(ChsError):  # query 2 alone holds 21 entries
+        gi.fill_chunks(off, 20)
+    with pytest.raises(ChsError):  # decreasing offsets
+        gi.fill_chunks(torch.tensor([0, 5, 4], dtype=torch.int64, device=dev), 10)
+    m = ctypes.c_int64(0)
+    b = (ctypes.c_int64 * 2)()
+    e = (ctypes.c_int64 * 2)()
+    st = lib().chs_fill_chunks(off.data_ptr(), 4, 22, b, e, 2, ctypes.byref(m), None)
+    assert st == 3 and m.value == 2  # CHS_E_CAPACITY: 2 ranges need 3 bounds
+    st = lib().chs_fill_chunks(off.data_ptr(), 4, 0, None, None, 0, ctypes.byref(m), None)
+    assert st == 1
+    # an empty set is one bound and no range
+    z = torch.zeros(1, dtype=torch.int64, device=dev)
+    assert gi.fill_chunks(z, 10) == ([0], [0])
