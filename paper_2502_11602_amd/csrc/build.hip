@@ -234,6 +234,58 @@ __global__ __launch_bounds__(kThreads) void k_hash_build(const uint64_t* __restr
   hash_insert(hk, hv, mask, ukeys[u], (int32_t)u);
 }
 
+// ---------------------------------------------------------------- column directory
+// Global key of the k = 0 voxel of the column holding voxel key `key` (the
+// tile found by its key offset: tiles own ascending key ranges).
+__device__ __forceinline__ uint64_t column_key(uint64_t key, const Grid* __restrict__ tiles,
+                                               int32_t ntiles) {
+  int32_t lo = 0, hi = ntiles - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (tiles[mid].koff <= key) lo = mid;
+    else hi = mid - 1;
+  }
+  const uint64_t nz = (uint64_t)tiles[lo].n[2];
+  return key - (key - tiles[lo].koff) % nz;
+}
+
+// mode 0: count the columns (first voxels of a column) into *ncol;
+// mode 1: insert each column with its first compact id;
+// mode 2: each column's last voxel writes the end of its id range.
+__global__ __launch_bounds__(kThreads) void k_columns(int mode, const uint64_t* __restrict__ ukeys,
+                                                      int64_t M, const int32_t* m_dev,
+                                                      const Grid* __restrict__ tiles,
+                                                      int32_t ntiles, uint64_t* ck, int2* cv,
+                                                      uint64_t mask, int32_t* ncol) {
+  const int64_t u = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t m = m_dev ? (int64_t)*m_dev : M;
+  if (u >= m) return;
+  const uint64_t c = column_key(ukeys[u], tiles, ntiles);
+  if (mode == 2) {
+    if (u + 1 < m && column_key(ukeys[u + 1], tiles, ntiles) == c) return;
+    uint64_t h = mix64(c) & mask;
+    while (ck[h] != c) h = (h + 1) & mask;  // inserted by mode 1
+    cv[h].y = (int32_t)(u + 1);
+    return;
+  }
+  if (u > 0 && column_key(ukeys[u - 1], tiles, ntiles) == c) return;
+  if (mode == 0) {
+    atomicAdd(ncol, 1);
+    return;
+  }
+  uint64_t h = mix64(c) & mask;
+  while (true) {
+    const unsigned long long prev = atomicCAS((unsigned long long*)&ck[h],
+                                              (unsigned long long)kEmptyKey,
+                                              (unsigned long long)c);
+    if (prev == kEmptyKey) {
+      cv[h] = make_int2((int32_t)u, (int32_t)u + 1);
+      return;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
 // ---------------------------------------------------------------- mixed map
 __global__ __launch_bounds__(kThreads) void k_slice_counts(const uint64_t* __restrict__ ukeys,
                                                            int64_t M, int64_t nz,
@@ -414,6 +466,45 @@ static chs_status build_sparse(chs_index ix) {
   return CHS_OK;
 }
 
+// The column directory of the sparse and mixed maps: a column's voxels are
+// adjacent in the compact order, so one probe per column of a search box
+// finds them all (instead of one probe per voxel).  Sized from the column
+// count, or, for framed builds (nothing read back), from the point count.
+static chs_status build_columns(chs_index ix) {
+  const Alloc& al = ix->al;
+  hipStream_t st = al.stream;
+  const int64_t mcap = ix->M >= 0 ? ix->M : ix->n;
+  int64_t ncol = mcap;
+  if (!ix->framed) {
+    Buf cnt(&al);
+    CHS_TRY(cnt.alloc(sizeof(int32_t)));
+    k_fill_i32<<<1, kThreads, 0, st>>>(cnt.as<int32_t>(), 1, 0);
+    CHS_LAUNCH_CHECK();
+    k_columns<<<grid_for(mcap), kThreads, 0, st>>>(0, ix->ukeys, mcap, ix->m_dev, ix->tiles_d,
+                                                     ix->ntiles, nullptr, nullptr, 0,
+                                                     cnt.as<int32_t>());
+    CHS_LAUNCH_CHECK();
+    int32_t h = 0;
+    CHS_HIP(hipMemcpyAsync(&h, cnt.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    CHS_HIP(hipStreamSynchronize(st));
+    ncol = h;
+  }
+  uint64_t cap = 64;
+  while (cap < (uint64_t)(2 * ncol)) cap <<= 1;  // load factor <= 0.5
+  ix->ccap = cap;
+  CHS_TRY(ix->own(&ix->ckeys, cap));
+  CHS_TRY(ix->own(&ix->cvals, cap));
+  k_fill_u64<<<1024, kThreads, 0, st>>>(ix->ckeys, (int64_t)cap, kEmptyKey);
+  CHS_LAUNCH_CHECK();
+  for (int mode = 1; mode <= 2; ++mode) {
+    k_columns<<<grid_for(mcap), kThreads, 0, st>>>(mode, ix->ukeys, mcap, ix->m_dev, ix->tiles_d,
+                                                     ix->ntiles, ix->ckeys, ix->cvals, cap - 1,
+                                                     nullptr);
+    CHS_LAUNCH_CHECK();
+  }
+  return CHS_OK;
+}
+
 static chs_status build_mixed(chs_index ix) {
   const Alloc& al = ix->al;
   hipStream_t st = al.stream;
@@ -588,6 +679,7 @@ static chs_status build_impl(chs_index ix, const double* xyz, int64_t n, const i
   if (ix->flavor == CHS_DENSE) CHS_TRY(build_dense(ix));
   if (ix->flavor == CHS_SPARSE) CHS_TRY(build_sparse(ix));
   if (ix->flavor == CHS_MIXED) CHS_TRY(build_mixed(ix));
+  if (ix->flavor != CHS_DENSE) CHS_TRY(build_columns(ix));
   // the processing order of "every point" queries (searches then plan
   // nothing for them)
   CHS_TRY(plan_every_point(ix, st));

@@ -96,6 +96,13 @@ struct Voxels {
   const uint8_t* slice_dense;  // MIXED: [n_z]
   const int64_t* slice_off;    // MIXED: [n_z] offset of a dense slice's table
   const int32_t* stab;         // MIXED: dense slice tables, compact id or -1
+  // SPARSE/MIXED column directory: open-addressing table keyed by the
+  // global key of a column's k = 0 voxel -> the compact ids [first, end) of
+  // its non-empty voxels (adjacent: the key is z-fastest, Eq. 7)
+  const uint64_t* ukeys;     // compact id -> global key, [M]
+  const uint64_t* ckeys;
+  const int2* cvals;
+  uint64_t cmask;
 };
 
 constexpr uint64_t kEmptyKey = ~0ull;
@@ -139,6 +146,9 @@ struct chs_index_s {
   uint8_t* slice_dense = nullptr;
   int64_t* slice_off = nullptr;
   int32_t* stab = nullptr;
+  uint64_t* ckeys = nullptr;  // column directory (SPARSE/MIXED)
+  int2* cvals = nullptr;
+  uint64_t ccap = 0;
   // cached processing order for "every point" queries: centres in waves of
   // at most 64 that never straddle two tiles
   float4* allq = nullptr;
@@ -171,6 +181,10 @@ struct chs_index_s {
     v.slice_dense = slice_dense;
     v.slice_off = slice_off;
     v.stab = stab;
+    v.ukeys = ukeys;
+    v.ckeys = ckeys;
+    v.cvals = cvals;
+    v.cmask = ccap ? ccap - 1 : 0;
     return v;
   }
   // index-owned allocation
@@ -262,44 +276,15 @@ __host__ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
   return x;
 }
 
-// Compact id of voxel g in the hash map, or -1 when the voxel is not stored.
-__device__ __forceinline__ int32_t hash_find(const uint64_t* __restrict__ hk,
-                                             const int32_t* __restrict__ hv, uint64_t mask,
-                                             uint64_t g) {
-  uint64_t h = mix64(g) & mask;
-  while (true) {
-    uint64_t k = hk[h];
-    if (k == g) return hv[h];
-    if (k == kEmptyKey) return -1;
-    h = (h + 1) & mask;
-  }
-}
-
-// Compact id of the non-empty voxel (i,j,k) of the tile, or -1 if it holds
-// no point.  The flavor FL is a compile-time constant: a run-time flavor
-// test inside the divergent probing loops below was once compiled into a
-// lane mask reused under a different exec mask, which sent sparse lookups
-// into the mixed flavor's slice table (a NULL pointer there).
-template <int FL>
-__device__ __forceinline__ int32_t voxel_id(const Voxels& vx, const Grid& g, int64_t i, int64_t j,
-                                            int64_t k) {
-  const uint64_t key =
-      g.koff + ((uint64_t)i * (uint64_t)g.n[1] + (uint64_t)j) * (uint64_t)g.n[2] + (uint64_t)k;
-  int32_t u;
-  if (FL == CHS_MIXED && vx.slice_dense[k]) {
-    const int64_t so = vx.slice_off[k];
-    u = so >= 0 ? vx.stab[so + i * g.n[1] + j] : -1;
-  } else {
-    u = hash_find(vx.hkeys, vx.hvals, vx.hmask, key);
-  }
-  return (u >= 0 && u < vx.M) ? u : -1;
-}
-
 // Stored-position range [b, e) of the voxels (i, j, k0..k1) of one column.
 // Because the global index is z-fastest (Eq. 7), these voxels are adjacent
 // in the stored order and their points form one contiguous run.  Voxel
 // coordinates outside the tile give an empty run, and every table value is
-// checked against the table's extent before use.
+// checked against the table's extent before use.  The flavor is a
+// compile-time constant (a run-time flavor test inside divergent lookup
+// loops was once compiled into a lane mask reused under another exec mask,
+// which sent sparse lookups into the mixed slice table, a NULL pointer
+// there).
 template <int FL>
 __device__ __forceinline__ void column_run(const Voxels& vx, const Grid& g, int64_t i, int64_t j,
                                            int64_t k0, int64_t k1, int32_t* b, int32_t* e) {
@@ -315,23 +300,37 @@ __device__ __forceinline__ void column_run(const Voxels& vx, const Grid& g, int6
     rb = vx.dstart[base + k0];
     re = vx.dstart[base + k1 + 1];
   } else {
-    int64_t k = k0;
-    int32_t u0 = -1;
-    for (; k <= k1; ++k) {
-      u0 = voxel_id<FL>(vx, g, i, j, k);
-      if (u0 >= 0) break;
-    }
-    if (u0 < 0) return;
-    int32_t u1 = u0;
-    for (int64_t kk = k1; kk > k; --kk) {
-      const int32_t u = voxel_id<FL>(vx, g, i, j, kk);
-      if (u >= 0) {
-        u1 = u;
+    // one probe of the column directory, then the column's voxels (sorted
+    // by key) bound the range: the first with k >= k0, the first with k > k1
+    uint64_t h = mix64(base) & vx.cmask;
+    int2 cr = make_int2(0, 0);
+    while (true) {
+      const uint64_t ck = vx.ckeys[h];
+      if (ck == base) {
+        cr = vx.cvals[h];
         break;
       }
+      if (ck == kEmptyKey) return;
+      h = (h + 1) & vx.cmask;
     }
+    if (cr.x < 0 || cr.y > vx.M || cr.x >= cr.y) return;
+    int32_t lo = cr.x, hi = cr.y;
+    const uint64_t kb = base + (uint64_t)k0, ke = base + (uint64_t)k1;
+    while (lo < hi) {  // first id with key >= kb
+      const int32_t mid = (lo + hi) >> 1;
+      if (vx.ukeys[mid] < kb) lo = mid + 1;
+      else hi = mid;
+    }
+    const int32_t u0 = lo;
+    hi = cr.y;
+    while (lo < hi) {  // first id with key > ke
+      const int32_t mid = (lo + hi) >> 1;
+      if (vx.ukeys[mid] <= ke) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo == u0) return;
     rb = vx.ustart[u0];
-    re = vx.ustart[u1 + 1];
+    re = vx.ustart[lo];
   }
   if (rb < 0) rb = 0;
   if (re > vx.npts) re = (int32_t)vx.npts;
