@@ -652,7 +652,9 @@ def run_tls(args):
     with the range from the scanner): 20 M points, 2 M query points drawn
     from the cloud, 0.25 m voxels, sparse and mixed maps.  Per radius (0.1,
     0.25, 0.5 m): the count pass over all 2 M queries, then the fill range by
-    range, each range's rows within a budget of --chunk-entries neighbour
+    range (the queries taken in the searches' processing order, so that each
+    range is spatially compact), each range's rows within a budget of
+    --chunk-entries neighbour
     entries (one reused buffer; at 0.5 m the relation holds about 1.5e11
     pairs, 600 GB of indices, far beyond one GPU's memory); then k-NN with
     k = 32 over the same queries.  Reported: neighbours/s and the method's
@@ -663,6 +665,7 @@ def run_tls(args):
 
     import cloudgen
     from paper_2502_11602_amd import GridIndex
+    from paper_2502_11602_amd.autotune import pick_radius_schedule
 
     print("[bench] generating TLS scan: 20 M points", file=sys.stderr, flush=True)
     c = cloudgen.config2()
@@ -670,18 +673,25 @@ def run_tls(args):
     n, nq = len(xyz), len(qidx)
     dev = torch.device("cuda:0")
     x = torch.from_numpy(xyz).to(dev)
-    q = torch.from_numpy(qidx).to(dev)
+    q_in = torch.from_numpy(qidx).to(dev)
     budget = int(args.chunk_entries)
     E = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     flavors = [f for f in args.tls_flavors.split(",") if f]
     out_fl = {}
     for fl in flavors:
-        e0, e1 = E(), E()
+        e0, e1, e2 = E(), E(), E()
         e0.record()
         gi = GridIndex(x, cell=0.25, flavor=fl)
+        if args.radius_schedule != "auto":
+            gi.set_radius_schedule(args.radius_schedule)
         e1.record()
+        # the queries in the searches' processing order, so that every fill
+        # range is spatially compact (rows then follow this order)
+        q = q_in[gi.query_order(q_in).long()]
+        e2.record()
         torch.cuda.synchronize()
-        rec = {"build_ms": e0.elapsed_time(e1), "radius": {}}
+        rec = {"build_ms": e0.elapsed_time(e1), "query_order_ms": e1.elapsed_time(e2),
+               "radius": {}}
 
         def one_pass(r):
             ev = [E() for _ in range(3)]
@@ -696,6 +706,11 @@ def run_tls(args):
             return ev, int(off[-1]), nch
 
         for r in c["radii"]:
+            if args.radius_schedule == "auto":
+                # the radius schedule of this batch, by timing both count passes
+                sched, sched_ms = pick_radius_schedule(gi, r, q)
+            else:
+                sched, sched_ms = args.radius_schedule, {}
             for _ in range(args.warmup):
                 one_pass(r)
             cms, fms, tot, nch = [], [], 0, 0
@@ -706,12 +721,13 @@ def run_tls(args):
             cm, fm = float(np.median(cms)), float(np.median(fms))
             byt = 12 * n + 12 * nq + 8 * (nq + 1) + 4 * tot
             rec["radius"][str(r)] = {
+                "schedule": sched, "schedule_count_ms": sched_ms,
                 "count_ms": cm, "chunked_fill_ms": fm, "ranges": nch, "neighbours": tot,
                 "mean_neighbours": tot / nq, "neighbours_per_s": tot / ((cm + fm) / 1e3),
                 "queries_per_s": nq / ((cm + fm) / 1e3), "algorithmic_bytes": byt,
                 "GB_per_s": byt / ((cm + fm) / 1e3) / 1e9,
                 "hbm_frac": byt / ((cm + fm) / 1e3) / 1e9 / PEAK_HBM_GBS}
-            print(f"[bench] tls {fl} r={r}: {tot} neighbours in {nch} ranges, count {cm:.1f} ms,"
+            print(f"[bench] tls {fl} r={r} ({sched}): {tot} neighbours in {nch} ranges, count {cm:.1f} ms,"
                   f" fill {fm:.1f} ms", file=sys.stderr, flush=True)
         k = c["k"]
         gi.knn(k, q)
@@ -860,6 +876,8 @@ def main():
     ap.add_argument("--chunk-entries", type=int, default=1 << 32,
                     help="tls: neighbour entries per fill range (4 B each)")
     ap.add_argument("--tls-flavors", default="sparse,mixed")
+    ap.add_argument("--radius-schedule", default="auto", choices=["auto", "tiles", "groups"],
+                    help="tls: the radius searches' work sharing")
     ap.add_argument("--agg-cell", type=float, default=0.5)
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--batch-r", type=float, default=1.0)

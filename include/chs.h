@@ -266,6 +266,16 @@ chs_status chs_radius_fill(chs_index index, const chs_queries* queries, float r,
                            const int64_t* offsets, int32_t* nbr, int64_t total,
                            hipStream_t stream);
 
+/* The order in which the searches process a query batch (Hilbert order of
+ * the centres' voxel columns, then z; per tile on a batched index): order
+ * (device, [nq] int32) receives the caller's query indices in that order.
+ * Queries reordered by it are spatially coherent in any consecutive range,
+ * which is what a range-by-range fill (chs_fill_chunks) needs to keep its
+ * ranges' query groups tight: ranges of a random query order each spread
+ * over the whole cloud.  Does not synchronise. */
+chs_status chs_query_order(chs_index index, const chs_queries* queries, int32_t* order,
+                           hipStream_t stream);
+
 /* Splits a counted set of nq queries into consecutive ranges that each
  * fill within max_entries neighbour entries (a memory budget for the fill's
  * output), as few as possible: bounds (host) receives q_0 = 0 < q_1 < ... <

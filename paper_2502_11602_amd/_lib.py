@@ -75,6 +75,7 @@ SIGNATURES = {
                                          c_float, c_void_p, ctypes.POINTER(c_int64), c_void_p]),
     "chs_kernel_fill_tiles": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_void_p, c_int32,
                                         c_float, c_void_p, c_void_p, c_int64, c_void_p]),
+    "chs_query_order": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_void_p, c_void_p]),
     "chs_fill_chunks": (c_int32, [c_void_p, c_int64, c_int64, c_void_p, c_void_p, c_int64,
                                   ctypes.POINTER(c_int64), c_void_p]),
     "chs_knn_tiles": (c_int32, [c_void_p, ctypes.POINTER(Queries), c_void_p, c_int32, c_float,

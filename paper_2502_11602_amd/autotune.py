@@ -167,3 +167,31 @@ class Autotuner:
             flavor = "sparse"
         schedule = min(sched_cost, key=sched_cost.get)
         return cells, flavor, schedule
+
+
+def pick_radius_schedule(index, r, queries=None, kernel="sphere", reps=2):
+    """Times the count pass of one query batch under both radius schedules
+    (64-query tiles, 8-query groups) and leaves the faster set on the index.
+    Returns (schedule, {schedule: ms}).  The best schedule depends on how
+    densely the queries sample the cloud: sparse query sets whose 64-query
+    tiles span little more than each query's own ball favour the tiles
+    (each candidate fetched once per wave through the scalar unit), dense
+    ones the groups' tighter candidate lists."""
+    times = {}
+    for sched in SCHEDULES:
+        index.set_radius_schedule(sched)
+        index.radius_count(r, queries, kernel=kernel, sync=False)
+        torch.cuda.synchronize()
+        best = math.inf
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            index.radius_count(r, queries, kernel=kernel, sync=False)
+            b.record()
+            torch.cuda.synchronize()
+            best = min(best, a.elapsed_time(b))
+        times[sched] = best
+    choice = min(times, key=times.get)
+    index.set_radius_schedule(choice)
+    return choice, times

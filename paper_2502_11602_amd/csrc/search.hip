@@ -195,6 +195,13 @@ static chs_status plan_impl(chs_index ix, int mode, const double* xyz, const int
   return CHS_OK;
 }
 
+__global__ __launch_bounds__(kThreads) void k_plan_order(const float4* __restrict__ q4, int64_t nq,
+                                                         int32_t* __restrict__ order) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= nq) return;
+  order[t] = (int32_t)(__float_as_uint(q4[t].w) & ~kInactive);
+}
+
 chs_status check_queries(chs_index ix, const chs_queries* qs) {
   if (!ix || !qs) {
     set_error("index or queries is NULL");
@@ -539,6 +546,24 @@ extern "C" chs_status chs_kernel_fill(chs_index ix, const chs_queries* qs, int32
   QueryPlan plan(&al);
   CHS_TRY(plan_queries(ix, qs, &plan, st));
   CHS_TRY(radius_fill_impl(ix, plan, kernel, r, offsets, nbr, total, st));
+  return CHS_OK;
+}
+
+extern "C" chs_status chs_query_order(chs_index ix, const chs_queries* qs, int32_t* order,
+                                      hipStream_t st) {
+  clear_error();
+  CHS_TRY(check_queries(ix, qs));
+  if (qs->nq > 0 && !order) {
+    set_error("order is NULL");
+    return CHS_E_INVALID;
+  }
+  if (qs->nq == 0) return CHS_OK;
+  Alloc al = ix->al;
+  al.stream = st;
+  QueryPlan plan(&al);
+  CHS_TRY(plan_queries(ix, qs, &plan, st));
+  k_plan_order<<<grid_for(plan.nq), kThreads, 0, st>>>(plan.q, plan.nq, order);
+  CHS_LAUNCH_CHECK();
   return CHS_OK;
 }
 

@@ -274,6 +274,16 @@ class GridIndex:
                                         _stream(stream)), "chs_kernel_fill")
         return nbr
 
+    def query_order(self, queries=None, stream=None):
+        """int32 [nq]: the caller's query indices in the order the searches
+        process them (spatially coherent; chs_query_order)."""
+        q, nq, keep = _queries(queries, self.n)
+        order = torch.empty(nq, dtype=torch.int32, device=self.device)
+        with _on(self.device, stream):
+            check(lib().chs_query_order(self._h, ctypes.byref(q), order.data_ptr() if nq else None,
+                                        _stream(stream)), "chs_query_order")
+        return order
+
     def fill_chunks(self, offsets, max_entries, stream=None):
         """Query ranges whose fills each hold at most max_entries entries
         (chs_fill_chunks): host lists bounds [q_0 = 0, ..., q_m = nq] and

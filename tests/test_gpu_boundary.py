@@ -285,3 +285,36 @@ def test_fill_chunks_rejects():
     # an empty set is one bound and no range
     z = torch.zeros(1, dtype=torch.int64, device=dev)
     assert gi.fill_chunks(z, 10) == ([0], [0])
+
+
+def test_query_order_and_ordered_ranges():
+    """chs_query_order is a permutation of the batch; counting and filling
+    the reordered queries range by range gives each query its own row."""
+    from paper_2502_11602_amd import GridIndex
+    dev = _dev()
+    xyz = _cloud()
+    gi = GridIndex(torch.from_numpy(xyz).to(dev), cell=1.0, flavor="sparse")
+    rng = np.random.default_rng(4)
+    q = torch.from_numpy(rng.choice(len(xyz), 6000, replace=False).astype(np.int32)).to(dev)
+    order = gi.query_order(q)
+    assert sorted(order.cpu().tolist()) == list(range(len(q)))
+    qs = q[order.long()]
+    off, nbr = gi.radius(2.0, q)
+    offc, nb = off.cpu().numpy(), nbr.cpu().numpy()
+    oc = order.cpu().numpy()
+    got = {}
+    offs = None
+    gen = gi.radius_chunked(2.0, qs, 3000)
+    for a, b, part in gen:
+        if offs is None:
+            offs, _ = gi.radius_count(2.0, qs)
+            so = offs.cpu().numpy()
+        p = part.cpu().numpy()
+        for t in range(a, b):
+            got[oc[t]] = np.sort(p[so[t] - so[a]:so[t + 1] - so[a]])
+    assert len(got) == len(q)
+    for i in range(0, len(q), 7):
+        np.testing.assert_array_equal(got[i], np.sort(nb[offc[i]:offc[i + 1]]))
+    # every-point queries: the build's plan order, a permutation of the points
+    allo = gi.query_order()
+    assert sorted(allo.cpu().tolist()) == list(range(len(xyz)))
