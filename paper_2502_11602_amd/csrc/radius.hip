@@ -503,11 +503,12 @@ __device__ __forceinline__ void radius_group_item(const RadiusArgs& A, const Ite
 
 // MULTI: per-item tile lookups and, if a counter is given, a persistent
 // loop over work items; otherwise one wave per item with tile 0's grid.
-// At most 64 VGPRs, so that eight waves share a SIMD (measured on the
-// 10 M-point tile: the r = 3 m count 2.28 -> 2.02 ms, fill 4.56 -> 4.39 ms;
-// the few spilled bytes of the fill cost less than the latency hidden).
+// Register budgets for more waves per SIMD (measured on the 10 M-point
+// tile): the count in 64 VGPRs, eight waves (r = 3 m 2.28 -> 2.02 ms); the
+// fill in 72, seven waves without spilling (4.56 -> 4.35 ms; held to 64 it
+// spilled 24 bytes per lane and read 80 % more from HBM).
 template <bool FILL, bool MULTI, int FL, int KS>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_radius_group(RadiusArgs A) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(FILL ? 7 : 8))) void k_radius_group(RadiusArgs A) {
   __shared__ int32_t s_cand[kWavesPerBlock * kCandCap];
   const int w = threadIdx.x / kWave, lane = lane_id();
   // (the wave index is uniform: keep the item and its queries in scalar
