@@ -72,6 +72,8 @@ def counter_traffic(radius):
 PROFILE_RUNS = {
     "agg": "rocprofv3 --kernel-trace --stats -d $R/gpurun_out/prof_agg -o agg -- "
            "python3 $R/bench.py --workload agg --steps 2",
+    "tls": "rocprofv3 --kernel-trace --stats -d $R/gpurun_out/prof_tls -o tls -- "
+           "python3 $R/bench.py --workload tls --steps 1 --warmup 0",
     "stats": "rocprofv3 --kernel-trace --stats -d $R/gpurun_out/prof_stats -o stats -- "
              "python3 $R/bench.py --steps 5 --warmup 2 --no-cpu-baseline --no-flavor-compare "
              "--no-kernel-compare",
@@ -158,6 +160,51 @@ def agg_profile_summary(stats_dir):
     out_dir = os.path.join(ROOT, "profiles")
     os.makedirs(out_dir, exist_ok=True)
     with open(os.path.join(out_dir, "gauss_agg_1m.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(json.dumps({"kernels": len(agg)}))
+
+
+def tls_profile_summary(stats_dir, bench_log):
+    """Write the committed summary of the TLS workload: kernel times from the
+    rocprofv3 run and the bench line that run printed."""
+    disp = _dispatches(_db(stats_dir))
+    agg = {}
+    for name, ms in disp:
+        a = agg.setdefault(name, [0, 0.0])
+        a[0] += 1
+        a[1] += ms
+    total = sum(v[1] for v in agg.values())
+    res = None
+    with open(bench_log) as fh:
+        for line in fh:
+            if line.startswith('{"metric"'):
+                res = json.loads(line)
+    lines = ["# TLS scan: 20 M points, 2 M query points, 0.25 m voxels (MI355X)", "",
+             "Command (from the repository root R, after `cd /tmp && export TMPDIR=/tmp`):", "",
+             "    " + PROFILE_RUNS["tls"], "",
+             "Per flavor (sparse, then mixed): the queries put in the searches' processing "
+             "order; per radius one count pass under each schedule (the faster is kept), then "
+             "the timed count over all queries and the fill range by range (at most %d "
+             "entries per range); then k-NN with k = 32." % (res or {}).get("chunk_entries", 0),
+             ""]
+    if res:
+        lines += ["| flavor | r (m) | schedule | neighbours | ranges | count ms | fill ms | "
+                  "neighbours/s |", "|---|---|---|---:|---:|---:|---:|---:|"]
+        for fl, rec in res["flavors"].items():
+            for r, v in rec["radius"].items():
+                lines.append(f"| {fl} | {r} | {v['schedule']} | {v['neighbours']:.3e} | "
+                             f"{v['ranges']} | {v['count_ms']:.1f} | {v['chunked_fill_ms']:.1f} | "
+                             f"{v['neighbours_per_s']:.2e} |")
+        lines += ["", "k-NN (k = 32, 2 M queries): " + ", ".join(
+            f"{fl} {rec['knn']['ms']:.1f} ms" for fl, rec in res["flavors"].items()),
+            "", f"Whole job: {res['value']:.3e} neighbours/s ({res['ms_per_step']:.0f} ms for "
+            "the three radii of the faster flavor).", ""]
+    lines += ["Kernel dispatches of the whole run (both flavors, schedule trials included):",
+              "", "| kernel | calls | total ms | avg ms | % |", "|---|---:|---:|---:|---:|"]
+    for name, (c, ms) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:16]:
+        lines.append(f"| `{name[:90]}` | {c} | {ms:.3f} | {ms / c:.4f} | {100 * ms / total:.1f} |")
+    out_dir = os.path.join(ROOT, "profiles")
+    with open(os.path.join(out_dir, "tls_scan_20m.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print(json.dumps({"kernels": len(agg)}))
 
@@ -895,6 +942,8 @@ def main():
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--profile-summary", nargs=2, metavar=("STATS_DIR", "PMC_ROOT"),
                     help="write the profiles/ summaries from rocprofv3 output directories")
+    ap.add_argument("--tls-profile-summary", nargs=2, metavar=("STATS_DIR", "BENCH_LOG"),
+                    help="write the TLS workload's profiles/ summary")
     ap.add_argument("--agg-profile-summary", metavar="STATS_DIR",
                     help="write the aggregation workload's profiles/ summary")
     args = ap.parse_args()
@@ -903,6 +952,9 @@ def main():
         return
     if args.agg_profile_summary:
         agg_profile_summary(args.agg_profile_summary)
+        return
+    if args.tls_profile_summary:
+        tls_profile_summary(*args.tls_profile_summary)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
