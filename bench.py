@@ -639,6 +639,36 @@ def run_batched(args):
         "cells_m": {"min": min(cells), "max": max(cells)},
     }
     print(json.dumps(out), flush=True)
+    if args.write_summary:
+        md = ["# Batched uneven tiles: one batched launch sequence, two captured graphs, "
+              "per-tile launches (MI355X)", "", "Command (repository root):", "",
+              "    python -u bench.py --workload batched --steps %d --warmup %d --write-summary"
+              % (args.steps, args.warmup), "",
+              f"Workload: {T} ALS-like tiles (sizes log-uniform 1e4..2e6, rescaled to about 60 M "
+              f"points; densities 2-20 pts/m^2); every point queries its own tile, radius "
+              f"r = {r} m (count + fill) and k-NN k = {k}; voxel edge, flavor and radius schedule "
+              f"per tile from the autotuner (edges {min(cells):.3g}-{max(cells):.4g} m; "
+              f"{flavor} flavor; schedule `{sched}`).", "",
+              "| quantity | value |", "|---|---|",
+              f"| n_points | {n} |", f"| tiles | {T} |",
+              f"| batched_ms | {t_batch * 1e3:.1f} |", f"| two_graph_step_ms | {t_graphs * 1e3:.1f} |",
+              f"| per_tile_ms | {t_tile * 1e3:.1f} |",
+              f"| speedup_vs_per_tile | {t_tile / t_batch:.2f} (two graphs: {t_tile / t_graphs:.2f}) |",
+              f"| graph_replay_fill_knn_ms | {t_graph_search * 1e3:.2f} |",
+              f"| identical_results | {same} |", f"| graph_identical | {same_graph} |",
+              f"| two_graph_identical | {same_graphs} |", f"| autotune_s | {tune_s:.1f} |",
+              f"| value (queries/s) | {2 * n / t_batch:.3e} |", "",
+              "- batched_ms: build + radius count + fill + k-NN for the whole batch (persistent "
+              "waves), eager calls;",
+              "- two_graph_step_ms: the same step as graph A (build from the tiles' bounding "
+              "boxes, which reads nothing back, + count + offsets) replayed, one read of the "
+              "neighbour total, then graph B (fill + k-NN) replayed;",
+              "- per_tile_ms: the same calls on separate per-tile indexes;",
+              "- graph_replay_fill_knn_ms: fill + k-NN replayed from a graph on the eager index;",
+              "- every variant's offsets, neighbour rows and k-NN lists equal the per-tile calls' "
+              "(`identical_results`, `*_identical`);", "- value = 2 x points / batched_ms."]
+        with open(os.path.join(ROOT, "profiles", "batched_tiles_60m.md"), "w") as fh:
+            fh.write("\n".join(md) + "\n")
 
 
 def run_sweep(args):
@@ -702,6 +732,28 @@ def run_sweep(args):
                       "n_points": n},
            "paper_min_bytes_per_point": 8, "best": best, "rows": rows}
     print(json.dumps(out), flush=True)
+    if args.write_summary:
+        md = ["# Cell size x 2D/3D x voxel map sweep, 10 M-point ALS tile (MI355X)", "",
+              "Command (repository root):", "",
+              "    python -u bench.py --workload sweep --write-summary", "",
+              "Every point a query; per configuration one warm and one measured pass: build, "
+              "radius search (count + fill) at 1 m and 3 m, k-NN at k = 16.  bytes/point is the "
+              "index's device memory right after the build (`chs_index_info`) divided by the "
+              "point count; the paper's minimum for a pointer-based index is 8 bytes per point, "
+              "this index keeps FP32 copies of the cloud in voxel order (16 B float4 + 12 B SoA) "
+              "and both permutations (8 B), so 36 B per point, plus the processing order of "
+              "every-point queries planned at build time (16 B per point) and the voxel maps "
+              "(the sparse and mixed maps: the voxel hash and the column directory).", "",
+              "| cell (m) | grid | map | build ms | r=1 m ms | r=3 m ms | k=16 ms | bytes/point | "
+              "non-empty voxels |", "|---:|---|---|---:|---:|---:|---:|---:|---:|"]
+        for r in rows:
+            md.append(f"| {r['cell_m']} | {r['dims']}D | {r['flavor']} | {r['build_ms']:.2f} | "
+                      f"{r['radius_1m_ms']:.2f} | {r['radius_3m_ms']:.2f} | {r['knn16_ms']:.2f} | "
+                      f"{r['device_bytes_per_point']:.1f} | {r['nonempty_voxels']} |")
+        md += ["", f"Fastest searches: {best['cell_m']} m, {best['dims']}D, {best['flavor']} "
+               f"(r = 1 m + r = 3 m + k = 16: {best['radius_1m_ms'] + best['radius_3m_ms'] + best['knn16_ms']:.2f} ms)."]
+        with open(os.path.join(ROOT, "profiles", "cell_size_sweep_als10m.md"), "w") as fh:
+            fh.write("\n".join(md) + "\n")
 
 
 def run_tls(args):
@@ -940,6 +992,8 @@ def main():
     ap.add_argument("--batch-r", type=float, default=1.0)
     ap.add_argument("--batch-k", type=int, default=16)
     ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--write-summary", action="store_true",
+                    help="sweep: also write its profiles/ summary")
     ap.add_argument("--profile-summary", nargs=2, metavar=("STATS_DIR", "PMC_ROOT"),
                     help="write the profiles/ summaries from rocprofv3 output directories")
     ap.add_argument("--tls-profile-summary", nargs=2, metavar=("STATS_DIR", "BENCH_LOG"),

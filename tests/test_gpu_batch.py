@@ -368,3 +368,27 @@ def test_tile_query_sets_match_oracle(flavor):
             oi, od = ox.knn(12, r_max=3.0, nthreads=8, **kw)
             np.testing.assert_array_equal(idx[a:b], oi)
             np.testing.assert_array_equal(d2[a:b], od)
+
+
+def test_pick_radius_schedule_times_both_and_keeps_results():
+    """autotune.pick_radius_schedule times one count pass per schedule,
+    leaves the faster set on the index, and the search then returns the
+    oracle's rows (sparse query set, so both schedules are plausible)."""
+    from paper_2502_11602_amd.autotune import pick_radius_schedule
+    dev = _dev()
+    c = cloudgen.config0()
+    from paper_2502_11602_amd import GridIndex
+    gi = GridIndex(torch.from_numpy(c["xyz"]).to(dev), cell=0.5, flavor="sparse")
+    q = c["queries"]
+    qt = torch.from_numpy(q).to(dev)
+    sched, times = pick_radius_schedule(gi, 1.0, qt)
+    assert set(times) == {"tiles", "groups"} and sched == min(times, key=times.get)
+    assert all(t > 0 for t in times.values())
+    off, nbr = gi.radius(1.0, qt)
+    ooff, onbr = oracle.OracleIndex(c["xyz"], 0.5, flavor="sparse").radius(1.0, pidx=q,
+                                                                          nthreads=8)
+    np.testing.assert_array_equal(off.cpu().numpy(), ooff)
+    o = off.cpu().numpy()
+    g = nbr.cpu().numpy()
+    for t in range(0, len(q), 37):
+        np.testing.assert_array_equal(np.sort(g[o[t]:o[t + 1]]), np.sort(onbr[ooff[t]:ooff[t + 1]]))
