@@ -259,20 +259,29 @@ __global__ __launch_bounds__(kThreads) void k_columns(int mode, const uint64_t* 
                                                       uint64_t mask, int32_t* ncol) {
   const int64_t u = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int64_t m = m_dev ? (int64_t)*m_dev : M;
-  if (u >= m) return;
-  const uint64_t c = column_key(ukeys[u], tiles, ntiles);
+  const bool in = u < m;
+  const uint64_t c = in ? column_key(ukeys[u], tiles, ntiles) : 0;
+  const bool head = in && !(u > 0 && column_key(ukeys[u - 1], tiles, ntiles) == c);
+  if (mode == 0) {
+    // one atomic per wave
+    const uint64_t b = __ballot(head);
+    if (lane_id() == 0 && b) atomicAdd(ncol, (int32_t)__popcll(b));
+    return;
+  }
+  if (!in) return;
   if (mode == 2) {
     if (u + 1 < m && column_key(ukeys[u + 1], tiles, ntiles) == c) return;
     uint64_t h = mix64(c) & mask;
-    while (ck[h] != c) h = (h + 1) & mask;  // inserted by mode 1
+    while (true) {  // inserted by mode 1 (an empty slot would mean it was not)
+      const uint64_t k = ck[h];
+      if (k == c) break;
+      if (k == kEmptyKey) return;
+      h = (h + 1) & mask;
+    }
     cv[h].y = (int32_t)(u + 1);
     return;
   }
-  if (u > 0 && column_key(ukeys[u - 1], tiles, ntiles) == c) return;
-  if (mode == 0) {
-    atomicAdd(ncol, 1);
-    return;
-  }
+  if (!head) return;
   uint64_t h = mix64(c) & mask;
   while (true) {
     const unsigned long long prev = atomicCAS((unsigned long long*)&ck[h],
