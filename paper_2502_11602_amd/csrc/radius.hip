@@ -460,29 +460,43 @@ __device__ __forceinline__ void radius_group_item(const RadiusArgs& A, const Ite
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int32_t c0 = p0; c0 < pend; c0 += kWave) {
-          const int32_t v = c0 + lane;
-          const bool valid = v < pend;
-          const int32_t pos = valid ? s_cand[v - p0] : 0;
-          const float4 P = A.pts[pos];
-          const uint64_t vmask = __ballot(valid);
-          const int32_t pid = __float_as_int(P.w) - poff;
+        // two candidates per lane per step (independent loads and tests
+        // in flight: r = 3 m count 2.03 -> 1.96 ms, fill 4.34 -> 4.20 ms);
+        // per query the first set's matches take their row slots first
+        for (int32_t c0 = p0; c0 < pend; c0 += 2 * kWave) {
+          const int32_t va = c0 + lane, vb = c0 + kWave + lane;
+          const bool valida = va < pend, validb = vb < pend;
+          const int32_t posa = valida ? s_cand[va - p0] : 0;
+          const int32_t posb = validb ? s_cand[vb - p0] : 0;
+          const float4 Pa = A.pts[posa];
+          const float4 Pb = A.pts[posb];
+          const uint64_t vmaska = __ballot(valida), vmaskb = __ballot(validb);
+          const int32_t pida = __float_as_int(Pa.w) - poff, pidb = __float_as_int(Pb.w) - poff;
 #pragma unroll
           for (int j = 0; j < kQGroup; ++j) {
             if (j >= ng) break;
-            const bool hit = inside<KS>(make_float4(qx[j], qy[j], qz[j], 0.f), P, rr, R);
-            const uint64_t m = __ballot(hit) & vmask;
+            const float4 qj = make_float4(qx[j], qy[j], qz[j], 0.f);
+            const bool hita = inside<KS>(qj, Pa, rr, R);
+            const bool hitb = inside<KS>(qj, Pb, rr, R);
+            const uint64_t ma = __ballot(hita) & vmaska;
+            const uint64_t mb = __ballot(hitb) & vmaskb;
             if (!FILL) {
-              cnt[j] += __popcll(m);
-            } else if (m) {
-              // the row cursor moves first (uniform, scalar registers), then
-              // the matching lanes store at their rank in the row, if the row
-              // has room
-              const int32_t w0 = wcnt[j];
-              wcnt[j] = w0 + __popcll(m);
-              const int32_t at = (int32_t)__builtin_amdgcn_mbcnt_hi(
-                  (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)w0));
-              if (hit && valid && at < rlen[j]) row[j][(uint32_t)at] = pid;
+              cnt[j] += __popcll(ma) + __popcll(mb);
+            } else {
+              if (ma) {
+                const int32_t w0 = wcnt[j];
+                wcnt[j] = w0 + __popcll(ma);
+                const int32_t at = (int32_t)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, (uint32_t)w0));
+                if (hita && valida && at < rlen[j]) row[j][(uint32_t)at] = pida;
+              }
+              if (mb) {
+                const int32_t w0 = wcnt[j];
+                wcnt[j] = w0 + __popcll(mb);
+                const int32_t at = (int32_t)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, (uint32_t)w0));
+                if (hitb && validb && at < rlen[j]) row[j][(uint32_t)at] = pidb;
+              }
             }
           }
         }
