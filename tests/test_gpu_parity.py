@@ -575,3 +575,55 @@ def test_query_groups(kernel, flavor):
     off, nbr = gw.radius(1.2, kernel=kernel)
     ooff, onbr = oracle.OracleIndex(w, 0.5, flavor=flavor).radius(1.2, nthreads=8, kernel=kernel)
     _assert_csr_equal(off, nbr, ooff, onbr)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("flavor", ["sparse", "mixed"])
+def test_config2_every_query_digests(config2_oracle, flavor):
+    """The 20 M-point TLS scan, 2 M query points, 0.25 m voxels, in the
+    launch configuration the benchmark times: the queries in the searches'
+    processing order, each radius counted over all of them, then filled
+    range by range within 2^32 entries per range (at 0.5 m the relation
+    holds 1.5e11 pairs), each range's rows hashed as it is filled; every
+    query's count and order-independent neighbour hash (sphere at 0.1, 0.25,
+    0.5 m) and every k = 32 row in order, summarised per block of 2^18
+    queries in the caller's order, equal the oracle's digests written by
+    tests/golden/make_config2_digests.py."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import _digest as D
+    from tests.conftest import ROOT
+    dev = _dev()
+    meta, sets = D.read_golden(os.path.join(ROOT, "tests", "golden", "config2_digests.txt"))
+    c = config2_oracle[0]
+    xyz, qidx = c["xyz"], c["queries"]
+    assert D.fingerprint(xyz) == meta["input"][0], "the generator no longer gives the digested cloud"
+    assert D.fingerprint(qidx.astype(np.float64)) == meta["input"][2]
+    assert int(meta["block"][0]) == D.BLOCK
+    gi = _gi()(torch.from_numpy(xyz).to(dev), cell=0.25, flavor=flavor)
+    from paper_2502_11602_amd.autotune import pick_radius_schedule
+    q = torch.from_numpy(qidx).to(dev)
+    order = gi.query_order(q).long()
+    qs = q[order]
+    nq = len(qidx)
+    for name, want in sets.items():
+        if name.startswith("knn_"):
+            idx, d2 = gi.knn(int(name[4:]), q)
+            cnt, h = D.row_hash_knn_t(idx, d2)
+            del idx, d2
+        else:
+            r = float(name.split("_")[1])
+            pick_radius_schedule(gi, r, qs)
+            off, _ = gi.radius_count(r, qs)
+            cnt = torch.empty(nq, dtype=torch.int64, device=dev)
+            h = torch.empty(nq, dtype=torch.int64, device=dev)
+            for a, b, part in gi.radius_chunked(r, qs, 1 << 32, offsets=off):
+                ca, ha = D.row_hash_csr_t(off[a:b + 1] - off[a], part)
+                cnt[order[a:b]] = ca
+                h[order[a:b]] = ha
+                del part
+            del off
+        got = D.block_digests_t(cnt, h)
+        bad = [w[0] for g, w in zip(got, want) if g != w]
+        assert len(got) == len(want) and not bad, f"{flavor} {name}: blocks {bad[:10]} differ"
