@@ -856,6 +856,29 @@ def run_tls(args):
         gi.close()
         del gi
         torch.cuda.empty_cache()
+    # k-NN by voxel edge: near the scanner a 0.25 m voxel holds hundreds of
+    # points, far more than 32 neighbours need (Section 5.3 sees k-NN suffer
+    # on dense non-ALS clouds); the edge is chosen by timing, as the
+    # autotuner does
+    knn_cells = {}
+    for cell in [float(v) for v in args.tls_knn_cells.split(",") if v]:
+        gk = GridIndex(x, cell=cell, flavor=flavors[0])
+        gk.knn(c["k"], q_in)
+        kms = []
+        for _ in range(max(args.steps, 1)):
+            a, b = E(), E()
+            a.record()
+            idx, d2 = gk.knn(c["k"], q_in)
+            b.record()
+            torch.cuda.synchronize()
+            kms.append(a.elapsed_time(b))
+            del idx, d2
+        knn_cells[str(cell)] = float(np.median(kms))
+        gk.close()
+        del gk
+        torch.cuda.empty_cache()
+        print(f"[bench] tls knn k={c['k']} at {cell} m voxels: {knn_cells[str(cell)]:.1f} ms",
+              file=sys.stderr, flush=True)
     best = min(out_fl, key=lambda f: sum(v["count_ms"] + v["chunked_fill_ms"]
                                          for v in out_fl[f]["radius"].values()))
     rr = out_fl[best]["radius"]
@@ -870,7 +893,8 @@ def run_tls(args):
            "config": {"workload": f"TLS scan, {n} points, {nq} query points, 0.25 m voxels, "
                                   f"{best} map (best of {flavors}); fill ranges of at most "
                                   f"{budget} entries", "n_points": n, "n_queries": nq},
-           "chunk_entries": budget, "flavors": out_fl}
+           "chunk_entries": budget, "flavors": out_fl,
+           "knn_by_cell_ms": knn_cells}
     print(json.dumps(out), flush=True)
 
 
@@ -985,6 +1009,8 @@ def main():
     ap.add_argument("--chunk-entries", type=int, default=1 << 32,
                     help="tls: neighbour entries per fill range (4 B each)")
     ap.add_argument("--tls-flavors", default="sparse,mixed")
+    ap.add_argument("--tls-knn-cells", default="0.1,0.25,0.5",
+                    help="tls: voxel edges at which k-NN is also timed")
     ap.add_argument("--radius-schedule", default="auto", choices=["auto", "tiles", "groups"],
                     help="tls: the radius searches' work sharing")
     ap.add_argument("--agg-cell", type=float, default=0.5)
