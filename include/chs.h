@@ -191,7 +191,7 @@ chs_status chs_tile_info(chs_index index, int32_t tile, chs_index_info_t* out /*
  * compares density growth with.  Results are identical; only the cost
  * differs. */
 /* CHS_OPT_FILL_STAGE (default 0): the radius fill stages each query's
- * matches in on-chip memory (LDS) before writing them out, 16, 24 or 32
+ * matches in on-chip memory (LDS) before writing them out, 16, 24, 32 or 64
  * entries per query; 0 picks the size from the mean row length total / nq.
  * Results are identical. */
 /* CHS_OPT_RADIUS_SCHEDULE (default 0): how the kernel-based searches share

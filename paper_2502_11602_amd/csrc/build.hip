@@ -827,8 +827,8 @@ extern "C" chs_status chs_index_set_option(chs_index ix, int32_t option, int64_t
     return CHS_OK;
   }
   if (option == CHS_OPT_FILL_STAGE) {
-    if (value != 0 && value != 16 && value != 24 && value != 32) {
-      set_error("fill stage must be 0 (by mean row length), 16, 24 or 32");
+    if (value != 0 && value != 16 && value != 24 && value != 32 && value != 64) {
+      set_error("fill stage must be 0 (by mean row length), 16, 24, 32 or 64");
       return CHS_E_INVALID;
     }
     ix->fill_stage = (int32_t)value;

@@ -179,8 +179,8 @@ class GridIndex:
               "chs_index_set_option")
 
     def set_fill_stage(self, entries=0):
-        """LDS entries per query of the radius fill (16, 24, 32; 0 = by the
-        mean row length); results are identical."""
+        """LDS entries per query of the radius fill (16, 24, 32, 64; 0 = by
+        the mean row length); results are identical."""
         check(lib().chs_index_set_option(self._h, 5, int(entries)), "chs_index_set_option")
 
     def coords(self, stream=None):
