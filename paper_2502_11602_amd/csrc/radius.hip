@@ -49,6 +49,12 @@ constexpr int kStageShort = 16, kStageMid = 24, kStageLong = 32, kStageHuge = 64
 // SIMD, which pays only for rows of thousands of entries: TLS scan at
 // 0.5 m, 76 k per row, 2.05 -> 1.89 s)
 constexpr int64_t kMidRows = 64, kLongRows = 256, kHugeRows = 8192;
+// Mean row length from which the flushes use non-temporal stores: with rows
+// of thousands of entries the output streams through L2 and, stored
+// normally, evicts the candidates the tiles re-read (TLS scan: 0.1 m fill
+// 147 -> 132 ms, 0.25 m 379 -> 315 ms, 0.5 m 1888 -> 1568 ms); with short
+// rows it is slower (ALS tile: r = 1 m 1.58 -> 1.67 ms).
+constexpr int64_t kStreamRows = 2048;
 
 // Where a lane's staged entries go: the row position and how many of them
 // are written (published once per flush, read by the half-waves).
@@ -58,7 +64,7 @@ struct alignas(16) RowSlot {
 };
 
 // FINAL: the lane's last flush, everything staged is written.
-template <bool FINAL, int ST>
+template <bool FINAL, int ST, bool NT>
 __device__ __forceinline__ void flush_stage(const int32_t* seg_base, RowSlot* rows, int lane,
                                             int& nb, int64_t& wpos, int64_t wend,
                                             int32_t* __restrict__ nbr) {
@@ -109,7 +115,10 @@ __device__ __forceinline__ void flush_stage(const int32_t* seg_base, RowSlot* ro
     for (int u = 0; u < kFlushUnroll; ++u)
 #pragma unroll
       for (int p = 0; p < PC; ++p)
-        if (ok[u] && 32 * p + i < r[u].cnt) nbr[r[u].pos + 32 * p + i] = v[u][p];
+        if (ok[u] && 32 * p + i < r[u].cnt) {
+          if (NT) __builtin_nontemporal_store(v[u][p], &nbr[r[u].pos + 32 * p + i]);
+          else nbr[r[u].pos + 32 * p + i] = v[u][p];
+        }
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -117,7 +126,7 @@ __device__ __forceinline__ void flush_stage(const int32_t* seg_base, RowSlot* ro
   nb -= used;
 }
 
-template <bool FILL, bool MULTI, int FL, int KS, int ST>
+template <bool FILL, bool MULTI, int FL, int KS, int ST, bool NT>
 __device__ __forceinline__ void radius_tile_item(const RadiusArgs& A, const Item& it, int lane,
                                             int32_t* seg_base, RowSlot* rows) {
   const Grid g = MULTI ? A.W.tiles[it.tile] : A.g0;
@@ -198,27 +207,27 @@ __device__ __forceinline__ void radius_tile_item(const RadiusArgs& A, const Item
                 my_seg[nb] = __float_as_int(P[u].w) - poff;
                 nb += inside<KS>(q, P[u], rr, R) ? 1 : 0;
               }
-              if (__ballot(nb > ST - kGroup)) flush_stage<false, ST>(seg_base, rows, lane, nb, wpos, wend, A.nbr);
+              if (__ballot(nb > ST - kGroup)) flush_stage<false, ST, NT>(seg_base, rows, lane, nb, wpos, wend, A.nbr);
             }
             for (; p < re; ++p) {
               const float4 P = load_const(cp, p);
               my_seg[nb] = __float_as_int(P.w) - poff;
               nb += inside<KS>(q, P, rr, R) ? 1 : 0;
-              if (__ballot(nb > ST - kGroup)) flush_stage<false, ST>(seg_base, rows, lane, nb, wpos, wend, A.nbr);
+              if (__ballot(nb > ST - kGroup)) flush_stage<false, ST, NT>(seg_base, rows, lane, nb, wpos, wend, A.nbr);
             }
           }
         }
       }
     }
   }
-  if (FILL) flush_stage<true, ST>(seg_base, rows, lane, nb, wpos, wend, A.nbr);
+  if (FILL) flush_stage<true, ST, NT>(seg_base, rows, lane, nb, wpos, wend, A.nbr);
   if (!FILL && in && (int64_t)qid < A.W.nq) A.counts[qid] = active ? cnt : 0;
 }
 
 // MULTI: per-item tile lookups and, if a counter is given, a persistent
 // loop over work items; otherwise one wave per item with tile 0's grid.
 // ST: entries per lane of the fill's stage (unused by the count pass)
-template <bool FILL, bool MULTI, int FL, int KS, int ST>
+template <bool FILL, bool MULTI, int FL, int KS, int ST, bool NT>
 __global__ __launch_bounds__(kThreads) void k_radius_tile(RadiusArgs A) {
   __shared__ int32_t s_stage[FILL ? kWavesPerBlock * kWave * Stage<ST>::stride : 1];
   __shared__ RowSlot s_rows[FILL ? kWavesPerBlock * kWave : 1];
@@ -228,13 +237,13 @@ __global__ __launch_bounds__(kThreads) void k_radius_tile(RadiusArgs A) {
   int64_t own = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
   if (!MULTI) {
     if (own < A.W.nwaves)
-      radius_tile_item<FILL, false, FL, KS, ST>(A, item_of(A.W, own), lane, seg_base, rows);
+      radius_tile_item<FILL, false, FL, KS, ST, NT>(A, item_of(A.W, own), lane, seg_base, rows);
     return;
   }
   while (true) {
     const int64_t item = next_item(A.W, &own, lane);
     if (item >= A.W.nwaves) break;
-    radius_tile_item<FILL, true, FL, KS, ST>(A, item_of(A.W, item), lane, seg_base, rows);
+    radius_tile_item<FILL, true, FL, KS, ST, NT>(A, item_of(A.W, item), lane, seg_base, rows);
   }
 }
 
@@ -553,30 +562,30 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(FILL ?
 }
 
 // ---------------------------------------------------------------- launches
-template <bool FILL, int KS, int ST>
+template <bool FILL, int KS, int ST, bool NT>
 static void launch_tile_ks(chs_index ix, unsigned nb, hipStream_t st, const RadiusArgs& A) {
   const bool mt = multi(ix);
   switch (ix->flavor) {
     case CHS_DENSE:
-      mt ? k_radius_tile<FILL, true, CHS_DENSE, KS, ST><<<nb, kThreads, 0, st>>>(A)
-         : k_radius_tile<FILL, false, CHS_DENSE, KS, ST><<<nb, kThreads, 0, st>>>(A);
+      mt ? k_radius_tile<FILL, true, CHS_DENSE, KS, ST, NT><<<nb, kThreads, 0, st>>>(A)
+         : k_radius_tile<FILL, false, CHS_DENSE, KS, ST, NT><<<nb, kThreads, 0, st>>>(A);
       break;
     case CHS_SPARSE:
-      mt ? k_radius_tile<FILL, true, CHS_SPARSE, KS, ST><<<nb, kThreads, 0, st>>>(A)
-         : k_radius_tile<FILL, false, CHS_SPARSE, KS, ST><<<nb, kThreads, 0, st>>>(A);
+      mt ? k_radius_tile<FILL, true, CHS_SPARSE, KS, ST, NT><<<nb, kThreads, 0, st>>>(A)
+         : k_radius_tile<FILL, false, CHS_SPARSE, KS, ST, NT><<<nb, kThreads, 0, st>>>(A);
       break;
     default:
-      mt ? k_radius_tile<FILL, true, CHS_MIXED, KS, ST><<<nb, kThreads, 0, st>>>(A)
-         : k_radius_tile<FILL, false, CHS_MIXED, KS, ST><<<nb, kThreads, 0, st>>>(A);
+      mt ? k_radius_tile<FILL, true, CHS_MIXED, KS, ST, NT><<<nb, kThreads, 0, st>>>(A)
+         : k_radius_tile<FILL, false, CHS_MIXED, KS, ST, NT><<<nb, kThreads, 0, st>>>(A);
   }
 }
 
-template <bool FILL, int ST>
+template <bool FILL, int ST, bool NT = false>
 static void launch_tile_st(chs_index ix, unsigned nb, hipStream_t st, const RadiusArgs& A,
                            int32_t kernel) {
-  if (kernel == CHS_KERNEL_CUBE) launch_tile_ks<FILL, kCube, ST>(ix, nb, st, A);
-  else if (kernel == CHS_KERNEL_CYLINDER) launch_tile_ks<FILL, kCylinder, ST>(ix, nb, st, A);
-  else launch_tile_ks<FILL, kSphere, ST>(ix, nb, st, A);
+  if (kernel == CHS_KERNEL_CUBE) launch_tile_ks<FILL, kCube, ST, NT>(ix, nb, st, A);
+  else if (kernel == CHS_KERNEL_CYLINDER) launch_tile_ks<FILL, kCylinder, ST, NT>(ix, nb, st, A);
+  else launch_tile_ks<FILL, kSphere, ST, NT>(ix, nb, st, A);
 }
 
 template <bool FILL>
@@ -592,7 +601,11 @@ static void launch_tiles(chs_index ix, unsigned nb, hipStream_t st, const Radius
       return;
     }
     if (ix->fill_stage == kStageHuge || (ix->fill_stage == 0 && mean_rows >= kHugeRows)) {
-      launch_tile_st<FILL, kStageHuge>(ix, nb, st, A, kernel);
+      launch_tile_st<FILL, kStageHuge, true>(ix, nb, st, A, kernel);
+      return;
+    }
+    if (ix->fill_stage == 0 && mean_rows >= kStreamRows) {
+      launch_tile_st<FILL, kStageLong, true>(ix, nb, st, A, kernel);
       return;
     }
     if (mean_rows >= kLongRows || ix->fill_stage == kStageLong) {

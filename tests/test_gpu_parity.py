@@ -523,6 +523,23 @@ def test_config1_every_query_digests(config1_cloud, flavor):
 
 
 # ---------------------------------------------------------------- every fill stage
+@pytest.mark.parametrize("n", [3000, 9000])
+@pytest.mark.parametrize("flavor", ["dense", "sparse"])
+def test_fill_long_rows_streaming(n, flavor):
+    """Rows of thousands of entries take the fill stages whose flushes use
+    non-temporal stores (mean row >= 2048: the 32-entry stage, >= 8192: the
+    64-entry one): a blob of n points in a 0.5 m cube, every point a query
+    at r = 1 m (rows of n entries), against the oracle."""
+    dev = _dev()
+    xyz = _blob(6, n)
+    g = _gi()(torch.from_numpy(xyz).to(dev), cell=0.1, flavor=flavor)
+    g.set_radius_schedule("tiles")
+    off, nbr = g.radius(1.0)
+    ooff, onbr = oracle.OracleIndex(xyz, 0.1, flavor=flavor).radius(1.0, nthreads=8)
+    assert int(ooff[-1]) == n * n
+    _assert_csr_equal(off, nbr, ooff, onbr)
+
+
 @pytest.mark.parametrize("stage", [16, 24, 32, 64])
 @pytest.mark.parametrize("kernel", ["sphere", "cube", "cylinder"])
 @pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
