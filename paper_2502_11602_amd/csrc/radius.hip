@@ -540,8 +540,9 @@ __device__ __forceinline__ void radius_group_item(const RadiusArgs& A, const Ite
 // loop over work items; otherwise one wave per item with tile 0's grid.
 // Register budgets for more waves per SIMD (measured on the 10 M-point
 // tile): the count in 64 VGPRs, eight waves (r = 3 m 2.28 -> 2.02 ms); the
-// fill in 72, seven waves without spilling (4.56 -> 4.35 ms; held to 64 it
-// spilled 24 bytes per lane and read 80 % more from HBM).
+// fill in 72, seven waves (4.56 -> 4.35 ms; held to 64 it spilled 24 bytes
+// per lane and read 80 % more from HBM; with two candidates per lane it
+// spills 12, and six waves without spilling are slower).
 template <bool FILL, bool MULTI, int FL, int KS>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(FILL ? 7 : 8))) void k_radius_group(RadiusArgs A) {
   __shared__ int32_t s_cand[kWavesPerBlock * kCandCap];
