@@ -188,8 +188,11 @@ chs_status chs_tile_info(chs_index index, int32_t tile, chs_index_info_t* out /*
  * of the candidates within it (Eq. 12), a query being done once k of them
  * lie within the radius.  2 = monotonic growth: as 1 with the radius grown
  * by the smallest voxel edge at every step, the baseline that Section 3.5
- * compares density growth with.  Results are identical; only the cost
- * differs. */
+ * compares density growth with.  3 = one query at a time: a wave grows each
+ * query's own visited box ring by ring and tests 64 candidates per step
+ * (for query sets that sample the cloud sparsely, whose 64-query tiles
+ * would stream the empty space between their queries).  Results are
+ * identical; only the cost differs. */
 /* CHS_OPT_FILL_STAGE (default 0): the radius fill stages each query's
  * matches in on-chip memory (LDS) before writing them out, 16, 24, 32 or 64
  * entries per query; 0 picks the size from the mean row length total / nq.

@@ -843,8 +843,9 @@ extern "C" chs_status chs_index_set_option(chs_index ix, int32_t option, int64_t
     return CHS_OK;
   }
   if (option == CHS_OPT_KNN_SCHEDULE) {
-    if (value < 0 || value > 2) {
-      set_error("k-NN schedule must be 0 (rings), 1 (density growth) or 2 (monotonic growth)");
+    if (value < 0 || value > 3) {
+      set_error("k-NN schedule must be 0 (rings), 1 (density growth), 2 (monotonic growth) "
+                "or 3 (one query at a time)");
       return CHS_E_INVALID;
     }
     ix->knn_sched = (int32_t)value;

@@ -120,7 +120,7 @@ struct chs_index_s {
   int64_t device_bytes = 0;
   int64_t max_dense = (int64_t)INT32_MAX - 1;
   bool persistent = false;  // searches pull waves from a work counter
-  int32_t knn_sched = 0;  // k-NN schedule: 0 rings, 1 density growth (Alg. 2), 2 monotonic
+  int32_t knn_sched = 0;  // k-NN schedule: 0 rings, 1 density growth (Alg. 2), 2 monotonic, 3 solo
   int32_t fill_stage = 0;    // radius fill: LDS entries per lane (0: by mean row length)
   int32_t radius_sched = 0;  // radius schedule: 0 auto, 1 64-query tiles, 2 8-query groups
   double cell_xy = 1.0;      // point-weighted mean of the tiles' smaller xy voxel edge

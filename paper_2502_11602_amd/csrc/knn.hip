@@ -509,6 +509,220 @@ void k_knn(KnnArgs A) {
   }
 }
 
+// ---------------------------------------------------------------- one query at a time
+// The solo schedule, for query sets that sample the cloud sparsely: a wave's
+// 64 queries are far apart, so the box holding all of them (which the ring
+// schedule streams) is mostly empty space between them.  Here the wave takes
+// its queries one at a time (centre in scalar registers), grows that query's
+// own visited box ring by ring (Alg. 2's taboo box, Section 3.5), packs the
+// new shell's column runs into an LDS list and tests 64 candidates per step,
+// one per lane.  The query's sorted list lives across the lanes (lane l
+// holds its l-th key); accepted candidates enter it by a bitonic sort and
+// merge across the lanes, or, when only a few are accepted, one by one.
+constexpr int kSoloCap = 1024;  // packed candidate positions per wave in LDS
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+  const int lo = __shfl((int)(uint32_t)v, src, kWave);
+  const int hi = __shfl((int)(uint32_t)(v >> 32), src, kWave);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+  const int lo = __shfl_xor((int)(uint32_t)v, m, kWave);
+  const int hi = __shfl_xor((int)(uint32_t)(v >> 32), m, kWave);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int src) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// The 64 lanes' keys sorted ascending across the lanes (bitonic network).
+__device__ __forceinline__ uint64_t lane_sort(uint64_t x, int lane) {
+#pragma unroll
+  for (int size = 2; size <= kWave; size <<= 1) {
+#pragma unroll
+    for (int j = size >> 1; j > 0; j >>= 1) {
+      const uint64_t y = shfl_xor64(x, j);
+      const bool keep_min = ((lane & j) == 0) == ((lane & size) == 0);
+      x = keep_min ? (x < y ? x : y) : (x < y ? y : x);
+    }
+  }
+  return x;
+}
+
+// The 64 smallest of two ascending lane lists, ascending: min(L[l], C[63-l])
+// is bitonic and holds them; a bitonic merge sorts it.
+__device__ __forceinline__ uint64_t lane_merge(uint64_t L, uint64_t C, int lane) {
+  const uint64_t cr = shfl64(C, kWave - 1 - lane);
+  uint64_t x = L < cr ? L : cr;
+#pragma unroll
+  for (int j = kWave / 2; j > 0; j >>= 1) {
+    const uint64_t y = shfl_xor64(x, j);
+    x = (lane & j) == 0 ? (x < y ? x : y) : (x < y ? y : x);
+  }
+  return x;
+}
+
+// Inserts key c (not in L, below L[63]) into the ascending lane list L.
+__device__ __forceinline__ uint64_t lane_insert(uint64_t L, uint64_t c, int lane) {
+  const int pos = __popcll(__ballot(L < c));
+  const uint64_t up = shfl64(L, lane > 0 ? lane - 1 : 0);
+  return lane < pos ? L : (lane == pos ? c : up);
+}
+
+template <bool MULTI, int FL>
+__device__ void knn_solo_item(const KnnArgs& A, const Item& it, int lane, int32_t* s_cand) {
+  const Grid g = MULTI ? A.W.tiles[it.tile] : A.g0;
+  const int32_t poff = (int32_t)g.poff;
+  const const_pts cq = as_const(A.W.q4);
+  for (int64_t t = it.t0; t < it.tend; ++t) {
+    const float4 q = load_const(cq, (int32_t)t);
+    const uint32_t wq = __float_as_uint(q.w);
+    const uint32_t qid = wq & ~kInactive;
+    if ((int64_t)qid >= A.W.nq) continue;
+    const bool active = !(wq & kInactive);
+    uint64_t L = ~0ull;  // lane l: the l-th key of the list
+    if (active) {
+      const float qc[3] = {q.x, q.y, q.z};
+      int32_t v[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        v[a] = a < g.dims ? (int32_t)voxel_clamped((double)qc[a], g.s[a], g.n[a]) : 0;
+      IBox V;
+      bool vempty = true;
+      uint64_t kthk = ~0ull;  // the k-th key (uniform)
+      for (int32_t d = 0;; ++d) {
+        IBox B;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          if (a >= g.dims) {
+            B.lo[a] = B.hi[a] = 0;
+            continue;
+          }
+          B.lo[a] = v[a] - d > 0 ? v[a] - d : 0;
+          B.hi[a] = v[a] + d < g.n[a] - 1 ? v[a] + d : (int32_t)(g.n[a] - 1);
+        }
+        // the shell B minus V: one column per lane, up to two runs each
+        const int32_t nj = B.hi[1] - B.lo[1] + 1;
+        const int32_t ncol = (B.hi[0] - B.lo[0] + 1) * nj;
+        for (int32_t cb = 0; cb < ncol; cb += kWave) {
+          const int32_t c = cb + lane;
+          int32_t b0 = 0, e0 = 0, b1 = 0, e1 = 0;
+          if (c < ncol) {
+            const int32_t ci = B.lo[0] + c / nj, cj = B.lo[1] + c % nj;
+            const bool inner = !vempty && ci >= V.lo[0] && ci <= V.hi[0] && cj >= V.lo[1] &&
+                               cj <= V.hi[1];
+            if (!inner) {
+              column_run<FL>(A.vx, g, ci, cj, B.lo[2], B.hi[2], &b0, &e0);
+            } else {
+              if (B.lo[2] < V.lo[2]) column_run<FL>(A.vx, g, ci, cj, B.lo[2], V.lo[2] - 1, &b0, &e0);
+              if (V.hi[2] < B.hi[2]) column_run<FL>(A.vx, g, ci, cj, V.hi[2] + 1, B.hi[2], &b1, &e1);
+            }
+          }
+          const int32_t l0 = e0 - b0, l1 = e1 - b1;
+          const int32_t incl = wave_incl_scan(l0 + l1, lane);
+          const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
+          for (int32_t p0 = 0; p0 < total; p0 += kSoloCap) {
+            const int32_t pend = total - p0 < kSoloCap ? total : p0 + kSoloCap;
+            const int32_t at = incl - l0 - l1;
+            for (int32_t k = 0; k < l0 + l1; ++k) {
+              const int32_t x = at + k - p0;
+              if (x >= 0 && x < pend - p0) s_cand[x] = k < l0 ? b0 + k : b1 + (k - l0);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int32_t c0 = p0; c0 < pend; c0 += kWave) {
+              const int32_t vv = c0 + lane;
+              const bool valid = vv < pend;
+              const float4 P = A.pts[valid ? s_cand[vv - p0] : 0];
+              const float dx = q.x - P.x, dy = q.y - P.y, dz = q.z - P.z;
+              const float D = (dx * dx + dy * dy) + dz * dz;
+              const uint64_t key =
+                  ((uint64_t)__float_as_uint(D) << 32) | (uint64_t)__float_as_uint(P.w);
+              const bool acc = valid && D <= A.rmax2 && key < kthk;
+              const uint64_t m = __ballot(acc);
+              if (m == 0) continue;
+              if (__popcll(m) <= 4) {
+                uint64_t mm = m;
+                while (mm) {
+                  const int src = __builtin_ctzll(mm);
+                  mm &= mm - 1;
+                  const uint64_t ck = readlane64(key, src);
+                  if (ck < readlane64(L, kWave - 1)) L = lane_insert(L, ck, lane);
+                }
+              } else {
+                L = lane_merge(L, lane_sort(acc ? key : ~0ull, lane), lane);
+              }
+              kthk = readlane64(L, A.k - 1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          }
+        }
+        V = B;
+        vempty = false;
+        bool whole = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          if (a >= g.dims) continue;
+          if (V.lo[a] > 0 || V.hi[a] < g.n[a] - 1) whole = false;
+        }
+        if (whole) break;
+        // every point outside V lies beyond the nearest face of V that is
+        // not on the grid boundary (as the ring schedule)
+        float thr = A.rmax2;
+        if (kthk != ~0ull) {
+          const float dk = __uint_as_float((uint32_t)(kthk >> 32));
+          thr = dk < thr ? dk : thr;
+        }
+        double lb = INFINITY;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          if (a >= g.dims) continue;
+          const double c = (double)qc[a];
+          if (V.lo[a] > 0) {
+            const double f = (double)V.lo[a] * g.s[a];
+            lb = fmin(lb, (c - f) - 0x1p-50 * (fabs(c) + fabs(f)));
+          }
+          if (V.hi[a] < g.n[a] - 1) {
+            const double f = (double)(V.hi[a] + 1) * g.s[a];
+            lb = fmin(lb, (f - c) - 0x1p-50 * (fabs(c) + fabs(f)));
+          }
+        }
+        lb = fmax(lb, 0.0);
+        const double lb2 = lb * lb;
+        if (lb2 >= 0x1p-100 && (double)thr < lb2 * (1.0 - kPadRel)) break;
+      }
+    }
+    if (lane < A.k) {
+      const bool ok = L != ~0ull;
+      A.idx[(int64_t)qid * A.k + lane] = ok ? (int32_t)(uint32_t)L - poff : -1;
+      A.d2[(int64_t)qid * A.k + lane] = ok ? __uint_as_float((uint32_t)(L >> 32)) : INFINITY;
+    }
+  }
+}
+
+template <bool MULTI, int FL>
+__global__ __launch_bounds__(kThreads) void k_knn_solo(KnnArgs A) {
+  __shared__ int32_t s_cand[kWavesPerBlock * kSoloCap];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  int64_t own = first_lane((int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w);
+  if (!MULTI) {
+    if (own < A.W.nwaves) knn_solo_item<false, FL>(A, item_of(A.W, own), lane, s_cand + w * kSoloCap);
+    return;
+  }
+  while (true) {
+    const int64_t item = next_item(A.W, &own, lane);
+    if (item >= A.W.nwaves) break;
+    knn_solo_item<true, FL>(A, item_of(A.W, item), lane, s_cand + w * kSoloCap);
+  }
+}
+
 // ---------------------------------------------------------------- launches
 template <int KC, int SCHED, int FL>
 static void launch_knn_f(chs_index ix, unsigned nb, hipStream_t st, const KnnArgs& A) {
@@ -540,7 +754,23 @@ static void launch_knn_kc(chs_index ix, unsigned nb, hipStream_t st, const KnnAr
   }
 }
 
+template <int FL>
+static void launch_knn_solo(chs_index ix, unsigned nb, hipStream_t st, const KnnArgs& A) {
+  if (multi(ix))
+    k_knn_solo<true, FL><<<nb, kThreads, 0, st>>>(A);
+  else
+    k_knn_solo<false, FL><<<nb, kThreads, 0, st>>>(A);
+}
+
 void launch_knn(chs_index ix, unsigned nb, hipStream_t st, const KnnArgs& A) {
+  if (ix->knn_sched == 3) {
+    switch (ix->flavor) {
+      case CHS_DENSE: launch_knn_solo<CHS_DENSE>(ix, nb, st, A); break;
+      case CHS_SPARSE: launch_knn_solo<CHS_SPARSE>(ix, nb, st, A); break;
+      default: launch_knn_solo<CHS_MIXED>(ix, nb, st, A);
+    }
+    return;
+  }
   if (A.k <= 8)
     launch_knn_kc<8>(ix, nb, st, A);
   else if (A.k <= 16)

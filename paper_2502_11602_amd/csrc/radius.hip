@@ -264,16 +264,6 @@ __global__ __launch_bounds__(kThreads) void k_radius_tile(RadiusArgs A) {
 constexpr int kQGroup = 8;
 constexpr int kCandCap = 1024;       // packed candidates per wave in LDS
 
-// Inclusive prefix sum over the wave.
-__device__ __forceinline__ int32_t wave_incl_scan(int32_t v, int lane) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int32_t o = __shfl_up(v, d, kWave);
-    if (lane >= d) v += o;
-  }
-  return v;
-}
-
 // Lane's rank among the set lanes of m below it.
 __device__ __forceinline__ int32_t lane_rank(uint64_t m) {
   return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),

@@ -704,8 +704,9 @@ extern "C" chs_status chs_knn_visited(chs_index ix, const chs_queries* qs, int32
     set_error("visited is NULL");
     return CHS_E_INVALID;
   }
-  if (multi(ix)) {
-    set_error("visited voxels are reported on a single-tile index without persistent waves");
+  if (multi(ix) || ix->knn_sched == 3) {
+    set_error("visited voxels are reported on a single-tile index without persistent waves, "
+              "under the ring or growth schedules");
     return CHS_E_UNSUPPORTED;
   }
   Alloc al = ix->al;

@@ -66,6 +66,16 @@ __device__ __forceinline__ int64_t next_item(const Waves& W, int64_t* own, int l
   return w;
 }
 
+// Inclusive prefix sum over the wave.
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t v, int lane) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int32_t o = __shfl_up(v, d, kWave);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
 // ---------------------------------------------------------------- tile geometry
 struct Tile {
   bool any;             // at least one active lane

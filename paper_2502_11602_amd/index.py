@@ -159,10 +159,11 @@ class GridIndex:
 
     def set_knn_schedule(self, schedule="rings"):
         """k-NN voxel schedule: "rings" (default), "density" (Alg. 2's
-        density-growth radius) or "monotonic" (the radius grows by the
-        smallest voxel edge per step); the results are identical."""
+        density-growth radius), "monotonic" (the radius grows by the
+        smallest voxel edge per step) or "solo" (one query at a time, for
+        sparse query sets); the results are identical."""
         check(lib().chs_index_set_option(self._h, 4, {"rings": 0, "density": 1,
-                                                      "monotonic": 2}[schedule]),
+                                                      "monotonic": 2, "solo": 3}[schedule]),
               "chs_index_set_option")
 
     def tile_info(self, t):

@@ -392,3 +392,44 @@ def test_pick_radius_schedule_times_both_and_keeps_results():
     g = nbr.cpu().numpy()
     for t in range(0, len(q), 37):
         np.testing.assert_array_equal(np.sort(g[o[t]:o[t + 1]]), np.sort(onbr[ooff[t]:ooff[t + 1]]))
+
+
+@pytest.mark.parametrize("flavor", ["dense", "sparse"])
+def test_batch_knn_solo_schedule(flavor):
+    """The one-query-at-a-time k-NN schedule on a batched (persistent)
+    index, every point and per-tile query sets, equals the ring schedule's
+    lists (which the per-tile oracle tests pin)."""
+    dev = _dev()
+    tiles, dens = _tiles(ntiles=12)
+    cells = [float(np.clip(np.sqrt(8.0 / d), 0.5, 2.0)) for d in dens]
+    ix, toff = _batch(tiles, cells, flavor, dev)
+    ir, dr = ix.knn(16)
+    ix.set_knn_schedule("solo")
+    i2, d2 = ix.knn(16)
+    assert torch.equal(ir, i2) and torch.equal(dr, d2)
+    rng = np.random.default_rng(9)
+    q = np.concatenate([rng.choice(len(t), 50, replace=False) for t in tiles]).astype(np.int32)
+    q_off = np.arange(0, 50 * (len(tiles) + 1), 50).tolist()
+    qt = torch.from_numpy(q).to(dev)
+    a_i, a_d = ix.knn_tiles(9, qt, q_off)
+    ix.set_knn_schedule("rings")
+    b_i, b_d = ix.knn_tiles(9, qt, q_off)
+    assert torch.equal(a_i, b_i) and torch.equal(a_d, b_d)
+
+
+def test_pick_knn_schedule_times_both():
+    """autotune.pick_knn_schedule times each schedule on the batch, keeps
+    the faster, and the lists are the oracle's."""
+    from paper_2502_11602_amd import GridIndex
+    from paper_2502_11602_amd.autotune import pick_knn_schedule
+    dev = _dev()
+    c = cloudgen.config0()
+    gi = GridIndex(torch.from_numpy(c["xyz"]).to(dev), cell=1.0)
+    q = c["queries"][:500]
+    qt = torch.from_numpy(q).to(dev)
+    sched, times = pick_knn_schedule(gi, 8, qt)
+    assert set(times) == {"rings", "solo"} and sched == min(times, key=times.get)
+    idx, d2 = gi.knn(8, qt)
+    oi, od = oracle.OracleIndex(c["xyz"], 1.0).knn(8, pidx=q, nthreads=8)
+    np.testing.assert_array_equal(idx.cpu().numpy(), oi)
+    np.testing.assert_array_equal(d2.cpu().numpy(), od)

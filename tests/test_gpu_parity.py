@@ -339,6 +339,50 @@ def test_knn_density_schedule(flavor):
         np.testing.assert_array_equal(d2.cpu().numpy(), od)
 
 
+@pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
+def test_knn_solo_schedule(flavor):
+    """The one-query-at-a-time schedule (CHS_OPT_KNN_SCHEDULE = 3) returns
+    the oracle's lists and the ring schedule's, exactly: config 0 at
+    k = 1, 16, 40, 64, sparse index queries, coordinate queries (inside and
+    outside the box) with an r_max cap, the adversarial clouds in 3D and
+    2D."""
+    dev = _dev()
+    c = cloudgen.config0()
+    gi = _gi()(torch.from_numpy(c["xyz"]).to(dev), cell=c["cell"], flavor=flavor)
+    ox = oracle.OracleIndex(c["xyz"], c["cell"], flavor=flavor)
+    q = torch.from_numpy(c["queries"]).to(dev)
+    for k in (1, 16, 40, 64):
+        ir, dr = gi.knn(k, q)
+        gi.set_knn_schedule("solo")
+        idx, d2 = gi.knn(k, q)
+        gi.set_knn_schedule("rings")
+        oi, od = ox.knn(k, pidx=c["queries"], nthreads=8)
+        np.testing.assert_array_equal(idx.cpu().numpy(), oi)
+        np.testing.assert_array_equal(d2.cpu().numpy(), od)
+        assert torch.equal(idx, ir) and torch.equal(d2, dr)
+    rng = np.random.default_rng(32)
+    qa = rng.uniform(c["xyz"].min(0) - 5.0, c["xyz"].max(0) + 5.0, (2000, 3))
+    gi.set_knn_schedule("solo")
+    idx, d2 = gi.knn(12, torch.from_numpy(qa).to(dev), r_max=1.5)
+    oi, od = ox.knn(12, r_max=1.5, qxyz=qa, nthreads=8)
+    np.testing.assert_array_equal(idx.cpu().numpy(), oi)
+    np.testing.assert_array_equal(d2.cpu().numpy(), od)
+    idx, d2 = gi.knn(9, torch.from_numpy(qa).to(dev))
+    oi, od = ox.knn(9, qxyz=qa, nthreads=8)
+    np.testing.assert_array_equal(idx.cpu().numpy(), oi)
+    np.testing.assert_array_equal(d2.cpu().numpy(), od)
+    for name in sorted(CLOUDS):
+        for dims, s in ((3, 0.3), (2, 2.5)):
+            xyz = CLOUDS[name](4)
+            g2 = _gi()(torch.from_numpy(xyz).to(dev), cell=s, dims=dims, flavor=flavor)
+            g2.set_knn_schedule("solo")
+            i2, e2 = g2.knn(20)
+            o2 = oracle.OracleIndex(xyz, s, dims=dims, flavor=flavor)
+            oi, od = o2.knn(20, nthreads=8)
+            np.testing.assert_array_equal(i2.cpu().numpy(), oi)
+            np.testing.assert_array_equal(e2.cpu().numpy(), od)
+
+
 def test_knn_edge_cases():
     dev = _dev()
     GI = _gi()
