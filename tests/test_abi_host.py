@@ -135,3 +135,32 @@ def test_knn_visited_rejects_null(L):
     q = Queries(None, None, 5)
     assert L.chs_knn_visited(None, ctypes.byref(q), 8, float("inf"), FAKE, FAKE, FAKE, None) == 1
     assert b"NULL" in L.chs_last_error()
+
+
+def test_header_compiles_and_links_as_c(tmp_path):
+    """The boundary is a C ABI: chs.h compiles as C99 and a C program links
+    against libchs.so and calls it (argument checks need no GPU)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "abi.c"
+    src.write_text(
+        '#include "chs.h"\n'
+        "int main(void) {\n"
+        "  chs_build_params p = {0};\n"
+        "  chs_index ix = 0;\n"
+        "  p.flavor = CHS_DENSE; p.dims = 3; p.cell[0] = p.cell[1] = p.cell[2] = 1.0;\n"
+        "  if (chs_build(0, 10, &p, 0, 0, &ix) != CHS_E_INVALID) return 1;\n"
+        "  if (chs_last_error()[0] == 0) return 2;\n"
+        "  return chs_version() ? 0 : 3;\n"
+        "}\n")
+    lib_dir = os.path.join(root, "paper_2502_11602_amd")
+    exe = tmp_path / "abi"
+    cmd = [gcc, "-std=c99", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(root, "include"),
+           "-I/opt/rocm/include", str(src), "-L" + lib_dir, "-l:libchs.so",
+           "-Wl,-rpath," + lib_dir, "-o", str(exe)]
+    subprocess.run(cmd, check=True, capture_output=True, timeout=120)
+    assert subprocess.run([str(exe)], timeout=60).returncode == 0
