@@ -384,6 +384,7 @@ def run_agg(args):
     import cloudgen
     from paper_2502_11602_amd import GridIndex, gauss_aggregate, neighbour_lists
     from paper_2502_11602_amd.agg import recentred
+    from paper_2502_11602_amd.autotune import pick_knn_schedule
 
     c = cloudgen.config4()
     dev = torch.device("cuda:0")
@@ -407,6 +408,9 @@ def run_agg(args):
 
     reps = max(2, args.steps + 1)
     ix = GridIndex(x64, cell=args.agg_cell, flavor="dense")
+    # the k-NN schedule of these lists, by timing both (a quarter of the
+    # points as centres: one query at a time usually wins)
+    knn_sched, knn_sched_ms = pick_knn_schedule(ix, K, q, r_max=c["r"])
     nbr = neighbour_lists(ix, q, k=K, r_max=c["r"])
     t_nbr = timed(lambda: neighbour_lists(ix, q, k=K, r_max=c["r"]), reps)
     x32 = recentred(ix)
@@ -455,6 +459,7 @@ def run_agg(args):
                                f"{C} channels, {K} nearest within {c['r']} m, sigma {sigma} m",
                    "cell_m": args.agg_cell, "valid_pairs": P},
         "neighbour_lists_ms": t_nbr,
+        "neighbour_lists_schedule": knn_sched, "schedule_trials_ms": knn_sched_ms,
         "passes": res,
         # against the method's minimum bytes (features read once); the
         # per-pair gather bytes (a feature row per valid pair) beside it

@@ -197,25 +197,28 @@ def pick_radius_schedule(index, r, queries=None, kernel="sphere", reps=2):
     return choice, times
 
 
-def pick_knn_schedule(index, k, queries=None, reps=2, schedules=("rings", "solo")):
+def pick_knn_schedule(index, k, queries=None, reps=2, schedules=("rings", "solo"),
+                      r_max=math.inf):
     """Times k-NN of one query batch under each schedule (by default the
     ring schedule, whose 64-query tiles share one visited box, and the
     one-query-at-a-time schedule) and leaves the faster set on the index.
     Returns (schedule, {schedule: ms}).  One query at a time wins for query
     sets that sample the cloud sparsely (10 M-point ALS tile, 1 % of the
-    points as queries: 1.1 vs 5.0 ms at k = 8), the rings for dense ones and
-    wherever queries must search far (the TLS scan's far field)."""
+    points as queries: 1.1 vs 5.0 ms at k = 8; the aggregation workload's
+    250 k centres among 1 M points, k = 64 within 0.5 m: 1.3 vs 1.6 ms), the
+    rings for dense ones and wherever queries must search far (the TLS
+    scan's far field)."""
     times = {}
     for sched in schedules:
         index.set_knn_schedule(sched)
-        index.knn(k, queries)
+        index.knn(k, queries, r_max=r_max)
         torch.cuda.synchronize()
         best = math.inf
         for _ in range(reps):
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record()
-            index.knn(k, queries)
+            index.knn(k, queries, r_max=r_max)
             b.record()
             torch.cuda.synchronize()
             best = min(best, a.elapsed_time(b))
