@@ -518,7 +518,7 @@ void k_knn(KnnArgs A) {
 // new shell's column runs into an LDS list and tests 64 candidates per step,
 // one per lane.  The query's sorted list lives across the lanes (lane l
 // holds its l-th key); accepted candidates enter it by a bitonic sort and
-// merge across the lanes, or, when only a few are accepted, one by one.
+// merge across the lanes, or, when at most 12 are accepted, one by one.
 constexpr int kSoloCap = 1024;  // packed candidate positions per wave in LDS
 
 __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
@@ -646,7 +646,9 @@ __device__ void knn_solo_item(const KnnArgs& A, const Item& it, int lane, int32_
               const bool acc = valid && D <= A.rmax2 && key < kthk;
               const uint64_t m = __ballot(acc);
               if (m == 0) continue;
-              if (__popcll(m) <= 4) {
+              // a few keys one by one (each a dependent shuffle), more by
+              // one sort and merge (27 dependent shuffle stages)
+              if (__popcll(m) <= 12) {
                 uint64_t mm = m;
                 while (mm) {
                   const int src = __builtin_ctzll(mm);
