@@ -770,8 +770,10 @@ def run_tls(args):
     range is spatially compact), each range's rows within a budget of
     --chunk-entries neighbour
     entries (one reused buffer; at 0.5 m the relation holds about 1.5e11
-    pairs, 600 GB of indices, far beyond one GPU's memory); then k-NN with
-    k = 32 over the same queries.  Reported: neighbours/s and the method's
+    pairs, 600 GB of indices, beyond one GPU's memory).  All tiles of a
+    range start at once, so a range lasts as long as its slowest tile: few,
+    large ranges (2^35 entries, 128 GiB, by default) keep those tails few.
+    Then k-NN with k = 32 over the same queries.  Reported: neighbours/s and the method's
     algorithmic bytes per second (cloud 12 B x N, centres 12 B x Q, offsets
     8 B x (Q + 1), indices 4 B x T) against the HBM peak."""
     import numpy as np
@@ -1011,8 +1013,9 @@ def main():
                     help="run one device-to-device copy of this size before the steps "
                          "(a known-size kernel for scaling hardware byte counters)")
     ap.add_argument("--workload", default="als10m", choices=["als10m", "batched", "sweep", "agg", "knnstats", "tls"])
-    ap.add_argument("--chunk-entries", type=int, default=1 << 32,
-                    help="tls: neighbour entries per fill range (4 B each)")
+    ap.add_argument("--chunk-entries", type=int, default=1 << 35,
+                    help="tls: neighbour entries per fill range (4 B each; the default "
+                         "buffer is 128 GiB of the GPU's 288 GB)")
     ap.add_argument("--tls-flavors", default="sparse,mixed")
     ap.add_argument("--tls-knn-cells", default="0.1,0.25,0.5",
                     help="tls: voxel edges at which k-NN is also timed")
