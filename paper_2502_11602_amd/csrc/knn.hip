@@ -261,9 +261,84 @@ __device__ int64_t own_voxels(const Grid& g, const float (&qc)[3], double r, dou
   }
 }
 
-template <int KC, bool MULTI, int FL, int SCHED, bool VIS>
+// A wave's queries come in processing order, which can leave a sparse
+// query set's region and re-enter it far away: one box over both stretches
+// would cover the gap, and every ring would grow it.  The lanes still to be
+// searched (todo) are therefore cut into clusters of consecutive lanes: a
+// cluster takes lanes while each next query's voxel column lies within
+// kClusterGap voxels (Chebyshev distance in x and y) of the cluster's
+// columns.  The clusters are searched one after the other, each with its
+// own box.  Heights are not compared: a column's ground and canopy points
+// share their column runs, and splitting them was slower.
+constexpr int32_t kClusterGap = 32;
+
+// The query's voxel column (x and y voxel coordinates, clamped).
+__device__ __forceinline__ void query_column(const Grid& g, const float (&qc)[3], int32_t (&qv)[2]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a) qv[a] = (int32_t)voxel_clamped((double)qc[a], g.s[a], g.n[a]);
+}
+
+// Whether the lanes in todo (not empty) hold a compact set of queries: every
+// query's voxel column, in FP32 voxel units, within kClusterGap of the
+// first such lane's along x and y.  Uniform; both launches of a search
+// evaluate it alike, and it costs one ballot (the launch that searches the
+// other waves evaluates it for every wave).
+__device__ __forceinline__ bool lanes_compact(uint64_t todo, const Grid& g, const float (&qc)[3],
+                                              int lane) {
+  const bool mine = (todo >> lane) & 1ull;
+  const int src = __builtin_ctzll(todo);
+  const float cx = floorf(qc[0] * (float)(1.0 / g.s[0]));
+  const float cy = floorf(qc[1] * (float)(1.0 / g.s[1]));
+  const float x0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cx), src));
+  const float y0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cy), src));
+  const float h = (float)kClusterGap;
+  return __ballot(mine && (fabsf(cx - x0) > h || fabsf(cy - y0) > h)) == 0ull;
+}
+
+__device__ __forceinline__ uint64_t lane_cluster(uint64_t todo, const Grid& g,
+                                                 const float (&qc)[3], int lane) {
+  if (lanes_compact(todo, g, qc, lane)) return todo;
+  int32_t qv[2];
+  query_column(g, qc, qv);
+  int l = __builtin_ctzll(todo);
+  uint64_t cm = 1ull << l;
+  uint64_t rest = todo & (todo - 1);
+  int32_t lo[2], hi[2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) lo[a] = hi[a] = __builtin_amdgcn_readlane(qv[a], l);
+  while (rest) {
+    l = __builtin_ctzll(rest);
+    int32_t v[2], d = 0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      v[a] = __builtin_amdgcn_readlane(qv[a], l);
+      const int32_t da = v[a] < lo[a] ? lo[a] - v[a] : (v[a] > hi[a] ? v[a] - hi[a] : 0);
+      d = da > d ? da : d;
+    }
+    if (d > kClusterGap) break;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      lo[a] = v[a] < lo[a] ? v[a] : lo[a];
+      hi[a] = v[a] > hi[a] ? v[a] : hi[a];
+    }
+    cm |= 1ull << l;
+    rest &= rest - 1;
+  }
+  return cm;
+}
+
+// Which waves a launch searches: kClAll every item with one box (the
+// persistent form), kClCompact the items whose queries are compact (one
+// box, no cluster loop, so the registers are those of the plain search;
+// the others go to a list), kClSplit the listed items, cluster by cluster,
+// with a grid of at most kSplitBlocks blocks.  The last two run as two
+// launches.
+constexpr int kClAll = 0, kClCompact = 1, kClSplit = 2;
+constexpr unsigned kSplitBlocks = 2048;
+
+template <int KC, bool MULTI, int FL, int SCHED, bool VIS, int CL>
 __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int lane,
-                                         uint64_t* seg) {
+                                         uint64_t* seg, int64_t wid) {
   const Grid g = MULTI ? A.W.tiles[it.tile] : A.g0;
   const int64_t t = it.t0 + lane;
   const bool in = t < it.tend;
@@ -271,10 +346,7 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
   const uint32_t wq = __float_as_uint(q.w);
   const uint32_t qid = wq & ~kInactive;
   const bool active = in && !(wq & kInactive) && (int64_t)qid < A.W.nq;
-  const Tile tb = tile_bounds(q, active);
   const const_pts cp = as_const(A.pts);
-  // lanes without a valid query accept nothing
-  const float rmax2 = active ? A.rmax2 : -1.0f;
   uint64_t best[KC];
 #pragma unroll
   for (int i = 0; i < KC; ++i) best[i] = ~0ull;
@@ -283,12 +355,15 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
   // voxels of the wave's visited box when this lane's list became final,
   // and of the lane's own box (written only when the caller asks for them)
   int64_t vis = -1, own_vis = -1;
-  if (tb.any) {
-    const float qc[3] = {q.x, q.y, q.z};
+  const float qc[3] = {q.x, q.y, q.z};
+  // one search over the lanes with act set; the others accept nothing
+  auto pass = [&](const bool act) __attribute__((always_inline)) {
+    const Tile tb = tile_bounds(q, act);
+    const float rmax2 = act ? A.rmax2 : -1.0f;
     // density schedule: the lane's radius, starting at the distance from
     // the query to the nearest wall of its voxel (Eq. 11)
     double rL = 0.0, smin = INFINITY;
-    bool done = !active;
+    bool done = !act;
     if (SCHED == kDensity) {
       rL = INFINITY;
 #pragma unroll
@@ -387,7 +462,7 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
         if (V.lo[a] > 0 || V.hi[a] < g.n[a] - 1) whole = false;
       }
       if (whole) {
-        if (VIS && vis < 0 && active) {
+        if (VIS && vis < 0 && act) {
           vis = box_voxels(V, g);
           own_vis = SCHED == kDensity ? own_voxels<KC>(g, qc, rL, smin, best, A.k, A.monotonic)
                                       : vis;
@@ -402,7 +477,7 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
         const uint32_t tb32 = __float_as_uint(T);
         done = done || (kthk != ~0ull && (uint32_t)(kthk >> 32) <= tb32) ||
                (double)A.rmax2 <= rL * rL;
-        if (VIS && done && vis < 0 && active) {
+        if (VIS && done && vis < 0 && act) {
           vis = box_voxels(V, g);
           own_vis = (double)A.rmax2 <= rL * rL
                         ? own_voxels<KC>(g, qc, rL, smin, best, 0, A.monotonic)
@@ -450,8 +525,8 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
       }
       lb = fmax(lb, 0.0);
       const double lb2 = lb * lb;
-      done = !active || (lb2 >= 0x1p-100 && (double)thr < lb2 * (1.0 - kPadRel));
-      if (VIS && done && vis < 0) vis = own_vis = box_voxels(V, g);
+      done = !act || (lb2 >= 0x1p-100 && (double)thr < lb2 * (1.0 - kPadRel));
+      if (VIS && done && vis < 0 && act) vis = own_vis = box_voxels(V, g);
       if (__ballot(!done) == 0ull) break;
       tau = wave_max(done ? -INFINITY : (double)thr);
       // next ring: grow the box by one voxel on every side
@@ -461,6 +536,28 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
         B.lo[a] = V.lo[a] > 0 ? V.lo[a] - 1 : 0;
         B.hi[a] = V.hi[a] < g.n[a] - 1 ? V.hi[a] + 1 : g.n[a] - 1;
       }
+    }
+  };
+  const uint64_t all = __ballot(active);
+  if (CL == kClAll) {
+    if (all) pass(active);
+  } else if (CL == kClCompact) {
+    // a wave whose lanes form one cluster searches here with one box
+    if (all && !lanes_compact(all, g, qc, lane) && lane_cluster(all, g, qc, lane) != all) {
+      // left to the second launch, which writes this item's rows
+      if (lane == 0) {
+        const int32_t at = atomicAdd(A.split, 1);
+        A.split[1 + at] = (int32_t)wid;
+      }
+      return;
+    }
+    if (all) pass(active);
+  } else {
+    uint64_t todo = all;
+    while (todo) {
+      const uint64_t cm = lane_cluster(todo, g, qc, lane);
+      todo &= ~cm;
+      pass(active && ((cm >> lane) & 1ull));
     }
   }
   if (VIS && active) {
@@ -489,23 +586,35 @@ __device__ __forceinline__ void knn_item(const KnnArgs& A, const Item& it, int l
 // 1 = persistent waves over a batched or persistent index, 2 = as 0 and
 // reporting the visited voxels (kept out of the other two, whose registers
 // it would cost).
-template <int KC, int MODE, int FL, int SCHED>
+template <int KC, int MODE, int FL, int SCHED, int CL>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(KC == 32 ? 4 : (KC == 16 ? 6 : (KC == 8 ? 8 : 1)))))
 void k_knn(KnnArgs A) {
   constexpr bool MULTI = MODE == 1, VIS = MODE == 2;
+  static_assert(!MULTI || CL == kClAll, "persistent waves search every item with one box");
   constexpr int kSeg = KnnBuf<KC>::on ? kWave * KnnBuf<KC>::stride : 1;
   __shared__ uint64_t s_buf[kWavesPerBlock * kSeg];
   const int w = threadIdx.x / kWave, lane = lane_id();
   uint64_t* seg = s_buf + w * kSeg + (KnnBuf<KC>::on ? lane * KnnBuf<KC>::stride : 0);
   int64_t own = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
   if (!MULTI) {
-    if (own < A.W.nwaves) knn_item<KC, false, FL, SCHED, VIS>(A, item_of(A.W, own), lane, seg);
+    if (CL == kClSplit) {
+      // the listed items (written by the previous launch on this stream)
+      const int64_t cnt = uniform(A.split[0]);
+      const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+      for (int64_t i = own; i < cnt; i += stride) {
+        const int64_t wv = uniform(A.split[1 + i]);
+        knn_item<KC, false, FL, SCHED, VIS, CL>(A, item_of(A.W, wv), lane, seg, wv);
+      }
+      return;
+    }
+    if (own < A.W.nwaves)
+      knn_item<KC, false, FL, SCHED, VIS, CL>(A, item_of(A.W, own), lane, seg, own);
     return;
   }
   while (true) {
     const int64_t item = next_item(A.W, &own, lane);
     if (item >= A.W.nwaves) break;
-    knn_item<KC, true, FL, SCHED, false>(A, item_of(A.W, item), lane, seg);
+    knn_item<KC, true, FL, SCHED, false, kClAll>(A, item_of(A.W, item), lane, seg, item);
   }
 }
 
@@ -728,12 +837,18 @@ __global__ __launch_bounds__(kThreads) void k_knn_solo(KnnArgs A) {
 // ---------------------------------------------------------------- launches
 template <int KC, int SCHED, int FL>
 static void launch_knn_f(chs_index ix, unsigned nb, hipStream_t st, const KnnArgs& A) {
-  if (multi(ix))
-    k_knn<KC, 1, FL, SCHED><<<nb, kThreads, 0, st>>>(A);
-  else if (A.visited)
-    k_knn<KC, 2, FL, SCHED><<<nb, kThreads, 0, st>>>(A);
-  else
-    k_knn<KC, 0, FL, SCHED><<<nb, kThreads, 0, st>>>(A);
+  // one wave per item: the compact items, then the listed others;
+  // persistent waves take every item
+  const unsigned nb2 = nb < kSplitBlocks ? nb : kSplitBlocks;
+  if (multi(ix)) {
+    k_knn<KC, 1, FL, SCHED, kClAll><<<nb, kThreads, 0, st>>>(A);
+  } else if (A.visited) {
+    k_knn<KC, 2, FL, SCHED, kClCompact><<<nb, kThreads, 0, st>>>(A);
+    k_knn<KC, 2, FL, SCHED, kClSplit><<<nb2, kThreads, 0, st>>>(A);
+  } else {
+    k_knn<KC, 0, FL, SCHED, kClCompact><<<nb, kThreads, 0, st>>>(A);
+    k_knn<KC, 0, FL, SCHED, kClSplit><<<nb2, kThreads, 0, st>>>(A);
+  }
 }
 
 template <int KC, int SCHED>

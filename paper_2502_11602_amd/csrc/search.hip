@@ -417,6 +417,20 @@ static chs_status launch_dims(chs_index ix, const QueryPlan& plan, hipStream_t s
   return CHS_OK;
 }
 
+// The list of items the one-wave-per-item k-NN leaves to its second launch
+// (a count, reset here, then up to one entry per wave); none for
+// persistent launches and the one-query-at-a-time schedule.
+static chs_status knn_split_list(chs_index ix, const QueryPlan& plan, hipStream_t st, Buf* buf,
+                                 int32_t** out) {
+  *out = nullptr;
+  if (multi(ix) || ix->knn_sched == 3) return CHS_OK;
+  CHS_TRY(buf->alloc(sizeof(int32_t) * (size_t)(plan.nwaves + 1)));
+  k_reset_counter<<<1, kWave, 0, st>>>(buf->as<int32_t>());
+  CHS_LAUNCH_CHECK();
+  *out = buf->as<int32_t>();
+  return CHS_OK;
+}
+
 static chs_status radius_count_impl(chs_index ix, const QueryPlan& plan, int32_t kernel, float r,
                                     int64_t* offsets, hipStream_t st) {
   Alloc al = ix->al;
@@ -495,8 +509,12 @@ chs_status knn_impl(chs_index ix, const chs_queries* qs, int32_t k, float r_max,
   int32_t* ctr;
   unsigned nb;
   CHS_TRY(launch_dims(ix, plan, st, &cbuf, &ctr, &nb));
+  Buf sbuf(&al);
+  int32_t* split;
+  CHS_TRY(knn_split_list(ix, plan, st, &sbuf, &split));
   KnnArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), k, rmax2, idx, d2,
             visited};
+  A.split = split;
   launch_knn(ix, nb, st, A);
   CHS_LAUNCH_CHECK();
   return CHS_OK;
@@ -785,7 +803,11 @@ extern "C" chs_status chs_knn_tiles(chs_index ix, const chs_queries* qs, const i
   int32_t* ctr;
   unsigned nb;
   CHS_TRY(launch_dims(ix, plan, st, &cbuf, &ctr, &nb));
+  Buf sbuf(&al);
+  int32_t* split;
+  CHS_TRY(knn_split_list(ix, plan, st, &sbuf, &split));
   KnnArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), k, rmax2, idx, d2};
+  A.split = split;
   launch_knn(ix, nb, st, A);
   CHS_LAUNCH_CHECK();
   return CHS_OK;

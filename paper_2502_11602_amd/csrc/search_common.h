@@ -216,6 +216,9 @@ struct KnnArgs {
   float* __restrict__ d2;
   int64_t* __restrict__ visited;  // optional: [nq][2] voxels visited per query
   int32_t monotonic;  // growth schedule: radius + smallest voxel edge per step
+  // one wave per item (not persistent): [0] a count, then the items whose
+  // queries are not compact, left by the first launch to the second
+  int32_t* split = nullptr;
 };
 
 // per-item tile lookups and persistent waves are needed by batched indexes

@@ -340,6 +340,59 @@ def test_knn_density_schedule(flavor):
 
 
 @pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
+@pytest.mark.parametrize("schedule", ["rings", "density"])
+def test_knn_query_sets_with_holes(flavor, schedule):
+    """Waves whose queries lie far apart (more than 16 voxels) are searched
+    cluster by cluster, each cluster with its own box: the lists equal the
+    oracle's.  Query sets: 64 points from two opposite corners of config 0
+    (one wave holding both), the same at 100 and 130 queries (a compact
+    wave beside a split one), a strip along each of two opposite edges,
+    and clusters of 3 alternating between corners (many small clusters)."""
+    dev = _dev()
+    c = cloudgen.config0()
+    xyz = c["xyz"]
+    gi = _gi()(torch.from_numpy(xyz).to(dev), cell=c["cell"], flavor=flavor)
+    gi.set_knn_schedule(schedule)
+    ox = oracle.OracleIndex(xyz, c["cell"], flavor=flavor)
+    rel = xyz[:, :2] - xyz[:, :2].min(0)
+    ext = rel.max(0)
+    near_a = np.flatnonzero((rel < 6.0).all(1))
+    near_b = np.flatnonzero((rel > ext - 6.0).all(1))
+    rng = np.random.default_rng(41)
+    sets = []
+    for na, nb in ((32, 32), (50, 50), (70, 60)):
+        sets.append(np.concatenate([rng.choice(near_a, na, replace=False),
+                                    rng.choice(near_b, nb, replace=False)]))
+    strip_a = np.flatnonzero(rel[:, 0] < 3.0)
+    strip_b = np.flatnonzero(rel[:, 0] > ext[0] - 3.0)
+    sets.append(np.concatenate([rng.choice(strip_a, 400, replace=False),
+                                rng.choice(strip_b, 400, replace=False)]))
+    alt = []
+    for i in range(12):
+        src = near_a if i % 2 == 0 else near_b
+        alt.append(rng.choice(src, 3, replace=False))
+    sets.append(np.concatenate(alt))
+    for q in sets:
+        q = q.astype(np.int32)
+        for k in (1, 8, 16, 32, 64):
+            idx, d2 = gi.knn(k, torch.from_numpy(q).to(dev))
+            oi, od = ox.knn(k, pidx=q, nthreads=8)
+            np.testing.assert_array_equal(idx.cpu().numpy(), oi, err_msg=f"nq={len(q)} k={k}")
+            np.testing.assert_array_equal(d2.cpu().numpy(), od, err_msg=f"nq={len(q)} k={k}")
+    # visited counts through the split launch: the lists are the same and
+    # every count lies between the query's own box and the grid
+    q = sets[0].astype(np.int32)
+    i2, e2, vis = gi.knn_visited(16, torch.from_numpy(q).to(dev))
+    oi, od = ox.knn(16, pidx=q, nthreads=8)
+    np.testing.assert_array_equal(i2.cpu().numpy(), oi)
+    vis = vis.cpu().numpy()
+    assert (vis[:, 0] >= 1).all() and (vis[:, 0] <= vis[:, 1]).all()
+    # a cluster's box is far smaller than the box over both corners
+    n = np.array(gi.info()["ncell"], np.int64)
+    assert (vis[:, 1] < np.prod(n) // 20).all(), (vis[:, 1].max(), np.prod(n))
+
+
+@pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
 def test_knn_solo_schedule(flavor):
     """The one-query-at-a-time schedule (CHS_OPT_KNN_SCHEDULE = 3) returns
     the oracle's lists and the ring schedule's, exactly: config 0 at
