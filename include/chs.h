@@ -381,11 +381,13 @@ chs_status chs_knn_visited(chs_index index, const chs_queries* queries, int32_t 
 /* chs_knn for callers that cannot allocate device memory (code under graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * arguments, results and errors as chs_knn, but no allocator is called.
- * Every temporary (the query plan with its sort buffers, the persistent work
- * counter) is carved from a fixed 32 MiB device array that the library holds
- * on each GPU it runs on until the process ends.  Index or coordinate
- * queries: nq <= 2^19 (CHS_E_CAPACITY beyond, checked before any device
- * work); "every point" queries use the order the build planned, any n.  Call
+ * Every temporary (the query plan with its sort buffers, the list of waves
+ * left to the search's second launch, the persistent work counter) is carved
+ * from a fixed 32 MiB device array that the library holds on each GPU it
+ * runs on until the process ends.  Index or coordinate queries: nq <= 2^19;
+ * "every point" queries use the order the build planned, n <= 2^28 on a
+ * plain index, any n on a batched or persistent one (CHS_E_CAPACITY beyond,
+ * checked before any device work).  Call
  * with the index's device current.  All calls on one GPU share that GPU's
  * array: two calls in flight at once (on different streams or threads) race
  * and give wrong results.  Does not synchronise. */

@@ -9,12 +9,15 @@ namespace chs {
 
 // ---------------------------------------------------------------- k-NN without allocation
 // chs_knn_noalloc takes every temporary of chs_knn (the query plan with its
-// sort buffers, the persistent work counter) from this fixed array instead of
-// an allocator.  Each GPU holds its own copy for the life of the process;
+// sort buffers, the list of waves left to the second launch, the persistent
+// work counter) from this fixed array instead of an allocator.  Each GPU holds its own copy for the life of the process;
 // host code reaches it only through the address hipGetSymbolAddress returns
 // for the device, never through the symbol itself.
 constexpr size_t kScratchBytes = (size_t)32 << 20;
 constexpr int64_t kNoallocMaxQueries = (int64_t)1 << 19;  // plan: <= 57 bytes per query
+// "every point" queries on a plain index: the wave list, 4 bytes per 64
+// points, within the array
+constexpr int64_t kNoallocMaxPoints = (int64_t)1 << 28;
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 struct Arena {
@@ -66,6 +69,12 @@ extern "C" chs_status chs_knn_noalloc(chs_index ix, const chs_queries* qs, int32
   if ((qs->xyz || qs->point_idx) && qs->nq > kNoallocMaxQueries) {
     set_error("chs_knn_noalloc: nq = %lld index or coordinate queries exceed the limit %lld",
               (long long)qs->nq, (long long)kNoallocMaxQueries);
+    return CHS_E_CAPACITY;
+  }
+  if (!qs->xyz && !qs->point_idx && ix->ntiles == 1 && !ix->persistent &&
+      ix->n > kNoallocMaxPoints) {
+    set_error("chs_knn_noalloc: every-point queries over %lld points exceed the limit %lld",
+              (long long)ix->n, (long long)kNoallocMaxPoints);
     return CHS_E_CAPACITY;
   }
   char* base = nullptr;
