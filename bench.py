@@ -123,18 +123,25 @@ def _counters(con):
     return [out[d] for d in sorted(out)]
 
 
-def _knn_first(name):
-    """A ring k-NN launch other than the second one of a search (the waves
-    the first listed, template argument CL = 2), which the per-kernel table
+def _second_launch(name):
+    """The second launch of a ring k-NN or radius-tile search (the waves the
+    first listed, template argument CL = 2), which the per-kernel table
     shows on its own."""
-    return "k_knn<" in name and not name.replace(" ", "").endswith(",2>(chs::KnnArgs)")
+    n = name.replace(" ", "")
+    return (("k_knn<" in n and n.endswith(",2>(chs::KnnArgs)")) or
+            ("k_radius_tile<" in n and n.endswith(",2>(chs::RadiusArgs)")))
+
+
+def _knn_first(name):
+    """A ring k-NN launch other than the second one of a search."""
+    return "k_knn<" in name and not _second_launch(name)
 
 
 def _hot_kernels(seq, radii, ks):
     """Label the search launches of one bench step, in their order: the count
     and fill of each radius, then k-NN per k.  seq: [(name, payload)]."""
-    counts = [x for x in seq if "k_radius" in x[0] and "<false" in x[0]]
-    fills = [x for x in seq if "k_radius" in x[0] and "<true" in x[0]]
+    counts = [x for x in seq if "k_radius" in x[0] and "<false" in x[0] and not _second_launch(x[0])]
+    fills = [x for x in seq if "k_radius" in x[0] and "<true" in x[0] and not _second_launch(x[0])]
     knns = [x for x in seq if _knn_first(x[0])]
     lab = []
     for i, r in enumerate(radii):
@@ -236,8 +243,10 @@ def profile_summary(stats_dir, pmc_root, radii=(0.5, 1.0, 2.0, 3.0), ks=(8, 16, 
     steps = 7  # 2 warm-up + 5 timed
     lab = {}
     # the labelled launches of every step, averaged over the steps
-    counts = [(nm, ms) for nm, ms in disp if "k_radius" in nm and "<false" in nm]
-    fills = [(nm, ms) for nm, ms in disp if "k_radius" in nm and "<true" in nm]
+    counts = [(nm, ms) for nm, ms in disp
+              if "k_radius" in nm and "<false" in nm and not _second_launch(nm)]
+    fills = [(nm, ms) for nm, ms in disp
+             if "k_radius" in nm and "<true" in nm and not _second_launch(nm)]
     knns = [(nm, ms) for nm, ms in disp if _knn_first(nm)]
     for i, r in enumerate(radii):
         c = counts[i::len(radii)]

@@ -126,9 +126,9 @@ __device__ __forceinline__ void flush_stage(const int32_t* seg_base, RowSlot* ro
   nb -= used;
 }
 
-template <bool FILL, bool MULTI, int FL, int KS, int ST, bool NT>
+template <bool FILL, bool MULTI, int FL, int KS, int ST, bool NT, int CL>
 __device__ __forceinline__ void radius_tile_item(const RadiusArgs& A, const Item& it, int lane,
-                                            int32_t* seg_base, RowSlot* rows) {
+                                            int32_t* seg_base, RowSlot* rows, int64_t wid) {
   const Grid g = MULTI ? A.W.tiles[it.tile] : A.g0;
   const int64_t t = it.t0 + lane;
   const bool in = t < it.tend;
@@ -136,12 +136,6 @@ __device__ __forceinline__ void radius_tile_item(const RadiusArgs& A, const Item
   const uint32_t wq = __float_as_uint(q.w);
   const uint32_t qid = wq & ~kInactive;
   const bool active = in && !(wq & kInactive) && (int64_t)qid < A.W.nq;
-  const Tile tb = tile_bounds(q, active);
-  // fl32(r*r); lanes without a valid query get negative bounds so that no
-  // candidate (D >= 0, |d| >= 0, or NaN) ever matches for them and they
-  // write nothing
-  const float R = active ? A.r * A.r : -1.0f;
-  const float rr = active ? A.r : -1.0f;
   const double pad = fmax((double)A.r * (1.0 + kPadRel), kPadAbs);
   const int32_t poff = (int32_t)g.poff;
   int32_t cnt = 0;
@@ -159,6 +153,13 @@ __device__ __forceinline__ void radius_tile_item(const RadiusArgs& A, const Item
     if (wend > A.total) wend = A.total;
     if (wpos < 0 || wpos > wend) wpos = wend = 0;
   }
+  // one search over the lanes with act set: fl32(r*r); the other lanes, and
+  // lanes without a valid query, get negative bounds so that no candidate
+  // (D >= 0, |d| >= 0, or NaN) ever matches for them and they write nothing
+  auto pass = [&](const bool act) __attribute__((always_inline)) {
+  const Tile tb = tile_bounds(q, act);
+  const float R = act ? A.r * A.r : -1.0f;
+  const float rr = act ? A.r : -1.0f;
   if (tb.any) {
     const VBox bx = voxel_box<KS>(g, tb.lo, tb.hi, pad);
     if (!bx.empty) {
@@ -220,6 +221,30 @@ __device__ __forceinline__ void radius_tile_item(const RadiusArgs& A, const Item
       }
     }
   }
+  };
+  const uint64_t all = __ballot(active);
+  if (CL == kClAll) {
+    pass(active);
+  } else if (CL == kClCompact) {
+    const float qc[3] = {q.x, q.y, q.z};
+    if (all && !lanes_compact(all, g, qc, lane) && lane_cluster(all, g, qc, lane) != all) {
+      // left to the second launch, which writes this item's counts or rows
+      if (lane == 0) {
+        const int32_t at = atomicAdd(A.split, 1);
+        A.split[1 + at] = (int32_t)wid;
+      }
+      return;
+    }
+    pass(active);
+  } else {
+    const float qc[3] = {q.x, q.y, q.z};
+    uint64_t todo = all;
+    while (todo) {
+      const uint64_t cm = lane_cluster(todo, g, qc, lane);
+      todo &= ~cm;
+      pass(active && ((cm >> lane) & 1ull));
+    }
+  }
   if (FILL) flush_stage<true, ST, NT>(seg_base, rows, lane, nb, wpos, wend, A.nbr);
   if (!FILL && in && (int64_t)qid < A.W.nq) A.counts[qid] = active ? cnt : 0;
 }
@@ -227,8 +252,9 @@ __device__ __forceinline__ void radius_tile_item(const RadiusArgs& A, const Item
 // MULTI: per-item tile lookups and, if a counter is given, a persistent
 // loop over work items; otherwise one wave per item with tile 0's grid.
 // ST: entries per lane of the fill's stage (unused by the count pass)
-template <bool FILL, bool MULTI, int FL, int KS, int ST, bool NT>
+template <bool FILL, bool MULTI, int FL, int KS, int ST, bool NT, int CL>
 __global__ __launch_bounds__(kThreads) void k_radius_tile(RadiusArgs A) {
+  static_assert(!MULTI || CL == kClAll, "persistent waves search every item with one box");
   __shared__ int32_t s_stage[FILL ? kWavesPerBlock * kWave * Stage<ST>::stride : 1];
   __shared__ RowSlot s_rows[FILL ? kWavesPerBlock * kWave : 1];
   const int w = threadIdx.x / kWave, lane = lane_id();
@@ -236,14 +262,27 @@ __global__ __launch_bounds__(kThreads) void k_radius_tile(RadiusArgs A) {
   RowSlot* rows = s_rows + (FILL ? w * kWave : 0);
   int64_t own = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
   if (!MULTI) {
+    if (CL == kClSplit) {
+      // the listed items (written by the previous launch on this stream)
+      const int64_t cnt = uniform(A.split[0]);
+      const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+      for (int64_t i = own; i < cnt; i += stride) {
+        const int64_t wv = uniform(A.split[1 + i]);
+        radius_tile_item<FILL, false, FL, KS, ST, NT, CL>(A, item_of(A.W, wv), lane, seg_base,
+                                                          rows, wv);
+      }
+      return;
+    }
     if (own < A.W.nwaves)
-      radius_tile_item<FILL, false, FL, KS, ST, NT>(A, item_of(A.W, own), lane, seg_base, rows);
+      radius_tile_item<FILL, false, FL, KS, ST, NT, CL>(A, item_of(A.W, own), lane, seg_base, rows,
+                                                        own);
     return;
   }
   while (true) {
     const int64_t item = next_item(A.W, &own, lane);
     if (item >= A.W.nwaves) break;
-    radius_tile_item<FILL, true, FL, KS, ST, NT>(A, item_of(A.W, item), lane, seg_base, rows);
+    radius_tile_item<FILL, true, FL, KS, ST, NT, kClAll>(A, item_of(A.W, item), lane, seg_base,
+                                                         rows, item);
   }
 }
 
@@ -553,21 +592,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(FILL ?
 }
 
 // ---------------------------------------------------------------- launches
+template <bool FILL, int FL, int KS, int ST, bool NT>
+static void launch_tile_fl(chs_index ix, unsigned nb, hipStream_t st, const RadiusArgs& A) {
+  // one wave per item: the compact items, then the listed others;
+  // persistent waves take every item
+  if (multi(ix)) {
+    k_radius_tile<FILL, true, FL, KS, ST, NT, kClAll><<<nb, kThreads, 0, st>>>(A);
+  } else {
+    const unsigned nb2 = nb < kSplitBlocks ? nb : kSplitBlocks;
+    k_radius_tile<FILL, false, FL, KS, ST, NT, kClCompact><<<nb, kThreads, 0, st>>>(A);
+    k_radius_tile<FILL, false, FL, KS, ST, NT, kClSplit><<<nb2, kThreads, 0, st>>>(A);
+  }
+}
+
 template <bool FILL, int KS, int ST, bool NT>
 static void launch_tile_ks(chs_index ix, unsigned nb, hipStream_t st, const RadiusArgs& A) {
-  const bool mt = multi(ix);
   switch (ix->flavor) {
-    case CHS_DENSE:
-      mt ? k_radius_tile<FILL, true, CHS_DENSE, KS, ST, NT><<<nb, kThreads, 0, st>>>(A)
-         : k_radius_tile<FILL, false, CHS_DENSE, KS, ST, NT><<<nb, kThreads, 0, st>>>(A);
-      break;
-    case CHS_SPARSE:
-      mt ? k_radius_tile<FILL, true, CHS_SPARSE, KS, ST, NT><<<nb, kThreads, 0, st>>>(A)
-         : k_radius_tile<FILL, false, CHS_SPARSE, KS, ST, NT><<<nb, kThreads, 0, st>>>(A);
-      break;
-    default:
-      mt ? k_radius_tile<FILL, true, CHS_MIXED, KS, ST, NT><<<nb, kThreads, 0, st>>>(A)
-         : k_radius_tile<FILL, false, CHS_MIXED, KS, ST, NT><<<nb, kThreads, 0, st>>>(A);
+    case CHS_DENSE: launch_tile_fl<FILL, CHS_DENSE, KS, ST, NT>(ix, nb, st, A); break;
+    case CHS_SPARSE: launch_tile_fl<FILL, CHS_SPARSE, KS, ST, NT>(ix, nb, st, A); break;
+    default: launch_tile_fl<FILL, CHS_MIXED, KS, ST, NT>(ix, nb, st, A);
   }
 }
 

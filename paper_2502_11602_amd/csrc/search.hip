@@ -417,13 +417,14 @@ static chs_status launch_dims(chs_index ix, const QueryPlan& plan, hipStream_t s
   return CHS_OK;
 }
 
-// The list of items the one-wave-per-item k-NN leaves to its second launch
-// (a count, reset here, then up to one entry per wave); none for
-// persistent launches and the one-query-at-a-time schedule.
-static chs_status knn_split_list(chs_index ix, const QueryPlan& plan, hipStream_t st, Buf* buf,
-                                 int32_t** out) {
+// The list of items a one-wave-per-item k-NN or radius-tile search leaves
+// to its second launch (a count, reset here, then up to one entry per
+// wave); none for persistent launches (and the k-NN's one-query-at-a-time
+// schedule, which has no tiles).
+static chs_status split_list(chs_index ix, const QueryPlan& plan, hipStream_t st, Buf* buf,
+                             int32_t** out) {
   *out = nullptr;
-  if (multi(ix) || ix->knn_sched == 3) return CHS_OK;
+  if (multi(ix)) return CHS_OK;
   CHS_TRY(buf->alloc(sizeof(int32_t) * (size_t)(plan.nwaves + 1)));
   k_reset_counter<<<1, kWave, 0, st>>>(buf->as<int32_t>());
   CHS_LAUNCH_CHECK();
@@ -443,8 +444,12 @@ static chs_status radius_count_impl(chs_index ix, const QueryPlan& plan, int32_t
     int32_t* ctr;
     unsigned nb;
     CHS_TRY(launch_dims(ix, plan, st, &cbuf, &ctr, &nb));
+    Buf sbuf(&al);
+    int32_t* split;
+    CHS_TRY(split_list(ix, plan, st, &sbuf, &split));
     RadiusArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), r,
                  counts.as<int32_t>(), nullptr, nullptr, 0};
+    A.split = split;
     launch_radius(false, ix, nb, st, A, kernel, 0);
     CHS_LAUNCH_CHECK();
   }
@@ -462,8 +467,12 @@ static chs_status radius_fill_impl(chs_index ix, const QueryPlan& plan, int32_t 
   int32_t* ctr;
   unsigned nb;
   CHS_TRY(launch_dims(ix, plan, st, &cbuf, &ctr, &nb));
+  Buf sbuf(&al);
+  int32_t* split;
+  CHS_TRY(split_list(ix, plan, st, &sbuf, &split));
   RadiusArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), r, nullptr,
                offsets, nbr, total};
+  A.split = split;
   launch_radius(true, ix, nb, st, A, kernel, total / plan.nq);
   CHS_LAUNCH_CHECK();
   return CHS_OK;
@@ -510,8 +519,10 @@ chs_status knn_impl(chs_index ix, const chs_queries* qs, int32_t k, float r_max,
   unsigned nb;
   CHS_TRY(launch_dims(ix, plan, st, &cbuf, &ctr, &nb));
   Buf sbuf(&al);
-  int32_t* split;
-  CHS_TRY(knn_split_list(ix, plan, st, &sbuf, &split));
+  int32_t* split = nullptr;
+  if (ix->knn_sched != 3) {
+    CHS_TRY(split_list(ix, plan, st, &sbuf, &split));
+  }
   KnnArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), k, rmax2, idx, d2,
             visited};
   A.split = split;
@@ -804,8 +815,10 @@ extern "C" chs_status chs_knn_tiles(chs_index ix, const chs_queries* qs, const i
   unsigned nb;
   CHS_TRY(launch_dims(ix, plan, st, &cbuf, &ctr, &nb));
   Buf sbuf(&al);
-  int32_t* split;
-  CHS_TRY(knn_split_list(ix, plan, st, &sbuf, &split));
+  int32_t* split = nullptr;
+  if (ix->knn_sched != 3) {
+    CHS_TRY(split_list(ix, plan, st, &sbuf, &split));
+  }
   KnnArgs A{make_waves(ix, plan, ctr), ix->grid(), ix->pts, ix->voxels(), k, rmax2, idx, d2};
   A.split = split;
   launch_knn(ix, nb, st, A);

@@ -95,6 +95,83 @@ __device__ __forceinline__ Tile tile_bounds(float4 q, bool active) {
   return t;
 }
 
+// ---------------------------------------------------------------- lane clusters
+// A wave's queries come in processing order, which can leave a sparse
+// query set's region and re-enter it far away: one box over both stretches
+// would cover the gap (and, for k-NN, every ring would grow it).  The lanes
+// still to be searched (todo) are therefore cut into clusters of
+// consecutive lanes: a
+// cluster takes lanes while each next query's voxel column lies within
+// kClusterGap voxels (Chebyshev distance in x and y) of the cluster's
+// columns.  The clusters are searched one after the other, each with its
+// own box.  Heights are not compared: a column's ground and canopy points
+// share their column runs, and splitting them was slower.
+constexpr int32_t kClusterGap = 32;
+
+// The query's voxel column (x and y voxel coordinates, clamped).
+__device__ __forceinline__ void query_column(const Grid& g, const float (&qc)[3], int32_t (&qv)[2]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a) qv[a] = (int32_t)voxel_clamped((double)qc[a], g.s[a], g.n[a]);
+}
+
+// Whether the lanes in todo (not empty) hold a compact set of queries: every
+// query's voxel column, in FP32 voxel units, within kClusterGap of the
+// first such lane's along x and y.  Uniform; both launches of a search
+// evaluate it alike, and it costs one ballot (the launch that searches the
+// other waves evaluates it for every wave).
+__device__ __forceinline__ bool lanes_compact(uint64_t todo, const Grid& g, const float (&qc)[3],
+                                              int lane) {
+  const bool mine = (todo >> lane) & 1ull;
+  const int src = __builtin_ctzll(todo);
+  const float cx = floorf(qc[0] * (float)(1.0 / g.s[0]));
+  const float cy = floorf(qc[1] * (float)(1.0 / g.s[1]));
+  const float x0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cx), src));
+  const float y0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cy), src));
+  const float h = (float)kClusterGap;
+  return __ballot(mine && (fabsf(cx - x0) > h || fabsf(cy - y0) > h)) == 0ull;
+}
+
+__device__ __forceinline__ uint64_t lane_cluster(uint64_t todo, const Grid& g,
+                                                 const float (&qc)[3], int lane) {
+  if (lanes_compact(todo, g, qc, lane)) return todo;
+  int32_t qv[2];
+  query_column(g, qc, qv);
+  int l = __builtin_ctzll(todo);
+  uint64_t cm = 1ull << l;
+  uint64_t rest = todo & (todo - 1);
+  int32_t lo[2], hi[2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) lo[a] = hi[a] = __builtin_amdgcn_readlane(qv[a], l);
+  while (rest) {
+    l = __builtin_ctzll(rest);
+    int32_t v[2], d = 0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      v[a] = __builtin_amdgcn_readlane(qv[a], l);
+      const int32_t da = v[a] < lo[a] ? lo[a] - v[a] : (v[a] > hi[a] ? v[a] - hi[a] : 0);
+      d = da > d ? da : d;
+    }
+    if (d > kClusterGap) break;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      lo[a] = v[a] < lo[a] ? v[a] : lo[a];
+      hi[a] = v[a] > hi[a] ? v[a] : hi[a];
+    }
+    cm |= 1ull << l;
+    rest &= rest - 1;
+  }
+  return cm;
+}
+
+// Which waves a launch of the 64-query k-NN or radius tiles searches:
+// kClAll every item with one box (the persistent form), kClCompact the
+// items whose queries are compact or form one cluster (one box, no cluster
+// loop, so the registers are those of the plain search; the others go to a
+// list), kClSplit the listed items, cluster by cluster, with a grid of at
+// most kSplitBlocks blocks.  The last two run as two launches.
+constexpr int kClAll = 0, kClCompact = 1, kClSplit = 2;
+constexpr unsigned kSplitBlocks = 2048;
+
 struct VBox {
   int64_t lo[3], hi[3];
   bool empty;
@@ -203,6 +280,9 @@ struct RadiusArgs {
   const int64_t* __restrict__ offsets;  // fill pass: [nq+1]
   int32_t* __restrict__ nbr;            // fill pass: [total]
   int64_t total;                        // fill pass: entries of nbr
+  // tiles, one wave per item (not persistent): [0] a count, then the items
+  // whose queries are not compact, left by the first launch to the second
+  int32_t* split = nullptr;
 };
 
 struct KnnArgs {

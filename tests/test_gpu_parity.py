@@ -339,6 +339,58 @@ def test_knn_density_schedule(flavor):
         np.testing.assert_array_equal(d2.cpu().numpy(), od)
 
 
+def _holes_sets(xyz, seed):
+    """Index query sets with holes in config 0: 64 points from two opposite
+    corners (one wave holding both), 100 and 130 of them (a compact wave
+    beside a split one), a strip along each of two opposite edges, and
+    clusters of 3 alternating between the corners (many small clusters)."""
+    rel = xyz[:, :2] - xyz[:, :2].min(0)
+    ext = rel.max(0)
+    near_a = np.flatnonzero((rel < 6.0).all(1))
+    near_b = np.flatnonzero((rel > ext - 6.0).all(1))
+    rng = np.random.default_rng(seed)
+    sets = []
+    for na, nb in ((32, 32), (50, 50), (70, 60)):
+        sets.append(np.concatenate([rng.choice(near_a, na, replace=False),
+                                    rng.choice(near_b, nb, replace=False)]))
+    strip_a = np.flatnonzero(rel[:, 0] < 3.0)
+    strip_b = np.flatnonzero(rel[:, 0] > ext[0] - 3.0)
+    sets.append(np.concatenate([rng.choice(strip_a, 400, replace=False),
+                                rng.choice(strip_b, 400, replace=False)]))
+    alt = []
+    for i in range(12):
+        src = near_a if i % 2 == 0 else near_b
+        alt.append(rng.choice(src, 3, replace=False))
+    sets.append(np.concatenate(alt))
+    return [q.astype(np.int32) for q in sets]
+
+
+@pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
+@pytest.mark.parametrize("kernel", ["sphere", "cube", "cylinder"])
+def test_radius_query_sets_with_holes(flavor, kernel):
+    """Radius tiles whose queries lie far apart are counted and filled
+    cluster by cluster (a second launch): CSR rows equal the oracle's, for
+    the whole set and range by range."""
+    dev = _dev()
+    c = cloudgen.config0()
+    xyz = c["xyz"]
+    gi = _gi()(torch.from_numpy(xyz).to(dev), cell=c["cell"], flavor=flavor)
+    gi.set_radius_schedule("tiles")
+    ox = oracle.OracleIndex(xyz, c["cell"], flavor=flavor)
+    for q in _holes_sets(xyz, 43):
+        for r in (0.5, 1.5):
+            qt = torch.from_numpy(q).to(dev)
+            off, nbr = gi.radius(r, qt, kernel=kernel)
+            ooff, onbr = ox.radius(r, pidx=q, nthreads=8, kernel=kernel)
+            _assert_csr_equal(off, nbr, ooff, onbr)
+    q = _holes_sets(xyz, 44)[3]
+    qt = torch.from_numpy(q).to(dev)
+    off, nbr = gi.radius(1.0, qt)
+    parts = [part.clone() for _, _, part in gi.radius_chunked(1.0, qt, int(off[-1]) // 3 + 1,
+                                                              offsets=off)]
+    assert torch.equal(torch.cat(parts), nbr)
+
+
 @pytest.mark.parametrize("flavor", ["dense", "sparse", "mixed"])
 @pytest.mark.parametrize("schedule", ["rings", "density"])
 def test_knn_query_sets_with_holes(flavor, schedule):
