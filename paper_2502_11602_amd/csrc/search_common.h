@@ -100,11 +100,10 @@ __device__ __forceinline__ Tile tile_bounds(float4 q, bool active) {
 // query set's region and re-enter it far away: one box over both stretches
 // would cover the gap (and, for k-NN, every ring would grow it).  The lanes
 // still to be searched (todo) are therefore cut into clusters of
-// consecutive lanes: a
-// cluster takes lanes while each next query's voxel column lies within
-// kClusterGap voxels (Chebyshev distance in x and y) of the cluster's
-// columns.  The clusters are searched one after the other, each with its
-// own box.  Heights are not compared: a column's ground and canopy points
+// consecutive lanes: a cluster takes lanes until the next query's voxel
+// column lies more than kClusterGap voxels (Chebyshev distance in x and y)
+// from the cluster's columns, and more than twice the cluster's extent.
+// The clusters are searched one after the other, each with its own box.  Heights are not compared: a column's ground and canopy points
 // share their column runs, and splitting them was slower.
 constexpr int32_t kClusterGap = 32;
 
@@ -151,7 +150,10 @@ __device__ __forceinline__ uint64_t lane_cluster(uint64_t todo, const Grid& g,
       const int32_t da = v[a] < lo[a] ? lo[a] - v[a] : (v[a] > hi[a] ? v[a] - hi[a] : 0);
       d = da > d ? da : d;
     }
-    if (d > kClusterGap) break;
+    // a jump counts only if it is also long against the cluster's extent
+    // (far-field queries spread over many voxels search best with one box)
+    const int32_t ext = (hi[0] - lo[0]) > (hi[1] - lo[1]) ? (hi[0] - lo[0]) : (hi[1] - lo[1]);
+    if (d > kClusterGap && d > 2 * ext) break;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       lo[a] = v[a] < lo[a] ? v[a] : lo[a];
